@@ -1,0 +1,201 @@
+"""ctypes binding of the FP64 oracle (test infrastructure, see package doc)."""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tbr_oracle.cpp")
+_LIB = os.path.join(_HERE, "libtbr_oracle.so")
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (plain IEEE FP64: no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
+               "-fno-fast-math", "-ffp-contract=off", "-o", _LIB + ".tmp", _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class OrcProgram(C.Structure):
+    _fields_ = [("n", C.c_int32), ("k", C.c_int32),
+                ("cx", C.c_void_p), ("cy", C.c_void_p), ("angle", C.c_void_p),
+                ("length", C.c_void_p), ("half_width", C.c_void_p),
+                ("logits", C.c_void_p), ("palette", C.c_void_p)]
+
+
+class OrcOpts(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32),
+                ("tau", C.c_double), ("tau_min", C.c_double),
+                ("tau_c", C.c_double), ("eps", C.c_double),
+                ("transport", C.c_int32)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        _lib = C.CDLL(_LIB)
+        vp, i64, dbl, i32 = C.c_void_p, C.c_int64, C.c_double, C.c_int
+        _lib.orc_psi.argtypes = [vp, dbl, i64, vp, vp, vp]
+        _lib.orc_phi.argtypes = [vp, i64, vp, vp]
+        _lib.orc_chart.argtypes = [vp, i64, vp, vp, vp]
+        _lib.orc_map_jacobian.argtypes = [i32, vp, dbl, i64, vp, vp]
+        _lib.orc_render.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
+        _lib.orc_render.restype = i32
+        _lib.orc_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
+        _lib.orc_backward.restype = i32
+        _lib.orc_hard_points.argtypes = [vp, vp, i64, vp, vp]
+        _lib.orc_num_threads.restype = i32
+        _lib.orc_set_num_threads.argtypes = [i32]
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def num_threads() -> int:
+    return _load().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    _load().orc_set_num_threads(int(n))
+
+
+def _stroke(stroke):
+    s = _f64(stroke).reshape(5)
+    return s
+
+
+def psi(stroke, pts, eps=1e-3):
+    """Backward map of one stroke (m_x, m_y, phi, L, r) at points [n,2]."""
+    s = _stroke(stroke)
+    p = _f64(pts).reshape(-1, 2)
+    out = np.empty_like(p)
+    rec = np.empty(len(p), dtype=np.int32)
+    _load().orc_psi(_ptr(s), float(eps), len(p), _ptr(p), _ptr(out), _ptr(rec))
+    return out, rec.astype(bool)
+
+
+def phi(stroke, pts):
+    """Exterior forward map of one stroke at points [n,2]."""
+    s = _stroke(stroke)
+    p = _f64(pts).reshape(-1, 2)
+    out = np.empty_like(p)
+    _load().orc_phi(_ptr(s), len(p), _ptr(p), _ptr(out))
+    return out
+
+
+def chart(stroke, pts):
+    """(sigma, w): distance to the segment and centred arclength fraction."""
+    s = _stroke(stroke)
+    p = _f64(pts).reshape(-1, 2)
+    sig = np.empty(len(p))
+    w = np.empty(len(p))
+    _load().orc_chart(_ptr(s), len(p), _ptr(p), _ptr(sig), _ptr(w))
+    return sig, w
+
+
+def map_jacobian(which, stroke, pts, eps=1e-3):
+    """Exact Jacobian [n,2,7] of psi ('psi') or Phi ('phi') w.r.t.
+    (x, y, m_x, m_y, phi, L, r)."""
+    s = _stroke(stroke)
+    p = _f64(pts).reshape(-1, 2)
+    jac = np.empty((len(p), 2, 7))
+    _load().orc_map_jacobian(0 if which == "psi" else 1, _ptr(s), float(eps), len(p),
+                             _ptr(p), _ptr(jac))
+    return jac
+
+
+class _Prog:
+    """Holds FP64 copies alive for the duration of a call."""
+
+    def __init__(self, prog):
+        self.arrs = {k: _f64(prog[k]) for k in
+                     ("cx", "cy", "angle", "length", "half_width", "logits", "palette")}
+        n = len(self.arrs["cx"])
+        k = self.arrs["palette"].reshape(-1, 3).shape[0]
+        assert self.arrs["logits"].size == n * k
+        self.s = OrcProgram(n, k, *[_ptr(self.arrs[f]) for f in
+                                    ("cx", "cy", "angle", "length", "half_width",
+                                     "logits", "palette")])
+        self.n, self.k = n, k
+
+
+def _opts(width, height, tau, tau_min, tau_c, eps, transport):
+    return OrcOpts(int(width), int(height), float(tau), float(tau_min), float(tau_c),
+                   float(eps), int(transport))
+
+
+def render(prog, width, height, *, tau=1e-3, tau_min=None, tau_c=0.0, eps=1e-3,
+           transport=True, pixels=None, soft=True, hard=True):
+    """Render a program (dict of arrays, see the synthetic generator) at pixel
+    centres. Returns a dict with 'soft' [n,3], 'hard' [n,3], 'label', 'owner',
+    'dmin', 'n_rec' (flat pixel order, or the order of ``pixels``)."""
+    if tau_min is None:
+        tau_min = 0.7 / width
+    pr = _Prog(prog)
+    o = _opts(width, height, tau, tau_min, tau_c, eps, transport)
+    pix = None if pixels is None else np.ascontiguousarray(np.asarray(pixels, dtype=np.int64))
+    n = width * height if pix is None else len(pix)
+    out = {}
+    if soft:
+        out["soft"] = np.empty((n, 3))
+        out["n_rec"] = np.empty(n, dtype=np.int32)
+    if hard:
+        out["hard"] = np.empty((n, 3))
+        out["label"] = np.empty(n, dtype=np.int32)
+        out["owner"] = np.empty(n, dtype=np.int32)
+        out["dmin"] = np.empty(n)
+    _load().orc_render(C.byref(pr.s), C.byref(o), n, _ptr(pix), _ptr(out.get("soft")),
+                       _ptr(out.get("hard")), _ptr(out.get("label")), _ptr(out.get("owner")),
+                       _ptr(out.get("dmin")), _ptr(out.get("n_rec")))
+    return out
+
+
+def backward(prog, width, height, grad_rgb, *, tau=1e-3, tau_min=None, tau_c=0.0, eps=1e-3,
+             transport=True, pixels=None):
+    """Vector-Jacobian product of the soft render with grad_rgb [n,3].
+    Returns dict: 'geom' [5,N] (m_x, m_y, phi, L, r), 'colour' [N,3],
+    'logits' [N,K], 'palette' [K,3]."""
+    if tau_min is None:
+        tau_min = 0.7 / width
+    pr = _Prog(prog)
+    o = _opts(width, height, tau, tau_min, tau_c, eps, transport)
+    pix = None if pixels is None else np.ascontiguousarray(np.asarray(pixels, dtype=np.int64))
+    n = width * height if pix is None else len(pix)
+    g = _f64(grad_rgb).reshape(n, 3)
+    geom = np.empty((5, pr.n))
+    colour = np.empty((pr.n, 3))
+    logits = np.empty((pr.n, pr.k))
+    palette = np.empty((pr.k, 3))
+    _load().orc_backward(C.byref(pr.s), C.byref(o), n, _ptr(pix), _ptr(g), _ptr(geom),
+                         _ptr(colour), _ptr(logits), _ptr(palette))
+    return {"geom": geom, "colour": colour, "logits": logits, "palette": palette}
+
+
+def hard_points(prog, pts, *, eps=1e-3, transport=True):
+    """Owner (0-based stroke index or -1) of arbitrary final-plane points."""
+    pr = _Prog(prog)
+    o = _opts(1, 1, 1e-3, 1e-3, 0.0, eps, transport)
+    p = _f64(pts).reshape(-1, 2)
+    own = np.empty(len(p), dtype=np.int32)
+    _load().orc_hard_points(C.byref(pr.s), C.byref(o), len(p), _ptr(p), _ptr(own))
+    return own
