@@ -1,0 +1,188 @@
+/* tbr.h -- C ABI of the deposition-stroke renderer on MI355X (gfx950).
+ *
+ * The operations are those of "TBR: Transport-Based Rendering with
+ * Deposition Strokes for Inverse Graphics" (arxiv 2609.08722):
+ *   - a program of N capsule strokes, each with segment, half-width and a
+ *     colour (Sec. 3, problem formulation; footprint K_i = closed capsule);
+ *   - the per-pixel chain x_N = x, x_{i-1} = psi_i(x_i), with coverage
+ *     evaluated at x_i, composited back to front (Sec. 3, Eq. chain and
+ *     Eq. render), with psi_i the capsule insertion's backward map
+ *     (Sec. 4, Eq. back, centred arclength, extension into the footprint,
+ *     and the implemented floor C >= (eps r)^2 of Sec. 5.2);
+ *   - hard coverage 1_{K_i} or the soft relaxation
+ *     sigmoid((r - sigma) / max(tau r, tau_min)) (Sec. 5.1, Eq. relax),
+ *     clamped at 1 - 1e-7 (Sec. 5.2);
+ *   - the replay adjoint (Sec. 5.2: Eq. rpos, Eq. rT, the side table of
+ *     positions where the floor binds, periodic checkpoints, Eq. adjstep
+ *     and Eq. adjparam), and one Adam step of the inverse problem on the
+ *     L2 data term (Sec. 3 Eq. inverse, Sec. 5.1 objective).
+ *
+ * Conventions shared by every call:
+ *   - Pointers named as device pointers are HIP device memory owned by the
+ *     caller; the library never allocates or frees device memory in these
+ *     calls (workspaces are passed in, sized by the *_bytes queries).
+ *   - Every call is ordered on the caller's hipStream_t `stream` (NULL = the
+ *     legacy default stream) and is asynchronous unless stated otherwise.
+ *   - Floats are IEEE FP32; images are row-major [H][W][3], pixel (i, j)
+ *     sampled at its centre ((j + .5) / W, (i + .5) / H) of the canvas
+ *     [0, 1]^2.
+ *   - A stroke is (centre m = (cx, cy), angle phi, length L, half-width r):
+ *     segment m +- (|L| / 2)(cos phi, sin phi); L = 0 is a drop. Its colour
+ *     is c = softmax(z / tau_c) P over the palette P (tau_c = 0: P[argmax z]).
+ *     The background is P[0].
+ *   - Scalar arguments are validated on the host: a violation returns
+ *     TBR_E_INVALID without launching anything, and tbr_last_error() says
+ *     why. Device array contents are not inspected (NaN propagates; r <= 0
+ *     is undefined). Launch failures return TBR_E_DEVICE. No call aborts.
+ *   - Calls are re-entrant given distinct workspaces.
+ */
+#ifndef TBR_H_
+#define TBR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tbr_status {
+  TBR_OK = 0,
+  TBR_PENDING = 1,        /* serving: request not finished yet */
+  TBR_E_INVALID = -1,     /* bad scalar argument, null pointer or short workspace */
+  TBR_E_NOMEM = -2,       /* serving arena cannot ever hold the request */
+  TBR_E_OVERFLOW = -3,    /* side table capacity exceeded (see tbr_tape_records) */
+  TBR_E_CAPACITY = -4,    /* serving queue full */
+  TBR_E_DEVICE = -5,      /* HIP runtime error */
+  TBR_E_CANCELLED = -6,   /* serving: request cancelled */
+  TBR_E_NOTFOUND = -7     /* serving: unknown ticket or program id */
+} tbr_status;
+
+/* Render modes (bit flags; both may be requested in one call). */
+enum { TBR_HARD = 1, TBR_SOFT = 2 };
+
+/* A stroke program (Sec. 3): device pointers, read-only.
+ * cx, cy, angle, length, half_width: [n_strokes]; logits: [n_strokes * n_palette]
+ * row-major; palette: [n_palette * 3] RGB, palette[0] is the background. */
+typedef struct tbr_program {
+  int32_t n_strokes;   /* N >= 0 */
+  int32_t n_palette;   /* 1 <= K <= 64 */
+  const float* cx;
+  const float* cy;
+  const float* angle;
+  const float* length;
+  const float* half_width;
+  const float* logits;
+  const float* palette;
+} tbr_program;
+
+/* Gradient outputs, same shapes as tbr_program's arrays (device, written). */
+typedef struct tbr_program_grad {
+  float* cx;
+  float* cy;
+  float* angle;
+  float* length;
+  float* half_width;
+  float* logits;
+  float* palette;
+} tbr_program_grad;
+
+typedef struct tbr_render_opts {
+  int32_t width, height;  /* 1 .. 16384 each */
+  float tau;              /* relative relaxation width, >= 0 (Eq. relax) */
+  float tau_min;          /* absolute floor of the width, > 0 for soft renders */
+  float tau_c;            /* colour temperature, >= 0 (0 = argmax colours) */
+  float eps_floor;        /* floor constant eps of C >= (eps r)^2, > 0 (paper: 1e-3) */
+  int32_t ckpt_interval;  /* position checkpoint interval k of the adjoint, >= 0 (0 = none) */
+  int32_t side_slots;     /* per-pixel side-table capacity, >= 1 when a tape is written */
+} tbr_render_opts;
+
+/* Per-group Adam settings for tbr_fit_step (Sec. 5.1, Table hyper). */
+typedef struct tbr_adam_opts {
+  float lr_centre, lr_angle, lr_length, lr_width, lr_logits, lr_palette;
+  float beta1, beta2, eps;
+  float r_lo, r_hi;  /* half-width clamp after the update */
+  float l_max;       /* |L| clamp after the update */
+  int32_t step;      /* 1-based step index for bias correction */
+} tbr_adam_opts;
+
+/* Workspace bytes for tbr_render. With with_tape != 0 (soft mode only) the
+ * workspace also holds the replay tape that tbr_render_backward consumes:
+ * the final state s_0, checkpoints of (x, T) every ckpt_interval states and
+ * the side table [side_slots][P] of positions where the floor bound. */
+size_t tbr_render_workspace_bytes(const tbr_render_opts* opts, int32_t n_strokes, int32_t mode,
+                                  int32_t with_tape);
+
+/* Forward render (Eq. chain + Eq. render).
+ * mode: TBR_SOFT and/or TBR_HARD.
+ * rgb [H*W*3]: soft composite if TBR_SOFT is set, else the hard colour; may
+ *   be NULL. label [H*W] (hard): palette index of the hard colour, 0 for
+ *   background; owner [H*W] (hard): 0-based index of the stroke owning the
+ *   pixel or -1; both may be NULL.
+ * with_tape: record the replay tape into the workspace (requires TBR_SOFT).
+ * Returns TBR_OK once launched; a side-table overflow is only detectable
+ * with tbr_tape_records. */
+tbr_status tbr_render(const tbr_program* prog, const tbr_render_opts* opts, int32_t mode,
+                      float* rgb, int32_t* label, int32_t* owner, void* workspace,
+                      size_t workspace_bytes, int32_t with_tape, void* stream);
+
+/* Largest number of side-table records any pixel needed in the last taped
+ * render of this workspace. SYNCHRONISES the stream. Returns TBR_E_OVERFLOW
+ * when it exceeds opts->side_slots (the tape is then incomplete and the
+ * render must be repeated with at least *max_records slots). */
+tbr_status tbr_tape_records(const void* workspace, size_t workspace_bytes,
+                            const tbr_render_opts* opts, int32_t n_strokes,
+                            int32_t* max_records, void* stream);
+
+/* Workspace bytes for tbr_render_backward (per-tile partial rows of the
+ * deterministic gradient reduction). */
+size_t tbr_backward_workspace_bytes(const tbr_render_opts* opts, int32_t n_strokes,
+                                    int32_t n_palette);
+
+/* Replay adjoint of the soft render (Sec. 5.2): vector-Jacobian product of
+ * the rendered image with grad_rgb [H*W*3] (dL/dR), written to every array
+ * of *grad (overwritten, not accumulated). tape_ws is the workspace of the
+ * preceding tbr_render(..., TBR_SOFT, ..., with_tape = 1) of the same
+ * program and options. Deterministic: no atomics, fixed summation order. */
+tbr_status tbr_render_backward(const tbr_program* prog, const tbr_render_opts* opts,
+                               const void* tape_ws, size_t tape_bytes, const float* grad_rgb,
+                               const tbr_program_grad* grad, void* workspace,
+                               size_t workspace_bytes, void* stream);
+
+/* Workspace bytes for tbr_fit_step (tape + reduction + seeds + gradients). */
+size_t tbr_fit_workspace_bytes(const tbr_render_opts* opts, int32_t n_strokes,
+                               int32_t n_palette);
+
+/* One optimisation step of the inverse problem with the pixel L2 data term
+ * L = mean((R - I*)^2) over the 3 H W values: soft render with tape, seed
+ * dL/dR, replay adjoint, deterministic reduction, and an Adam update.
+ * params: packed device vector [cx N | cy N | angle N | length N |
+ *   half_width N | logits N*K | palette K*3], updated in place.
+ * grads: same layout, written (may be NULL: kept in the workspace).
+ * adam_m, adam_v: Adam moments, same layout, updated in place.
+ * target_rgb [H*W*3]; loss: device scalar, written (value before the update).
+ * Half-width is clamped to [r_lo, r_hi], |length| to l_max, palette to [0,1]. */
+tbr_status tbr_fit_step(int32_t n_strokes, int32_t n_palette, float* params, float* grads,
+                        float* adam_m, float* adam_v, const tbr_adam_opts* adam,
+                        const tbr_render_opts* opts, const float* target_rgb, float* loss,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
+/* Optional timing hook for benchmarks. While set on the calling thread,
+ * every launch of the kernel named `kernel` ("trace_soft", "trace_hard" or
+ * "replay") made by a tbr_* call on this thread is bracketed by
+ * hipEventRecord(begin) / hipEventRecord(end) on that call's stream (with
+ * several launches, the last pair stands). begin and end are hipEvent_t
+ * handles owned by the caller. kernel = NULL clears the hook. */
+tbr_status tbr_set_timing_events(const char* kernel, void* begin, void* end);
+
+/* Thread-local description of the last non-OK status of this thread. */
+const char* tbr_last_error(void);
+
+/* Library version string. */
+const char* tbr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TBR_H_ */

@@ -1,0 +1,91 @@
+"""ctypes view of the C ABI in include/tbr.h (argument marshalling only)."""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtbr.so")
+
+TBR_OK, TBR_PENDING = 0, 1
+TBR_E_INVALID, TBR_E_NOMEM, TBR_E_OVERFLOW, TBR_E_CAPACITY = -1, -2, -3, -4
+TBR_E_DEVICE, TBR_E_CANCELLED, TBR_E_NOTFOUND = -5, -6, -7
+TBR_HARD, TBR_SOFT = 1, 2
+
+STATUS_NAMES = {0: "TBR_OK", 1: "TBR_PENDING", -1: "TBR_E_INVALID", -2: "TBR_E_NOMEM",
+                -3: "TBR_E_OVERFLOW", -4: "TBR_E_CAPACITY", -5: "TBR_E_DEVICE",
+                -6: "TBR_E_CANCELLED", -7: "TBR_E_NOTFOUND"}
+
+
+class TbrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Program(C.Structure):
+    _fields_ = [("n_strokes", C.c_int32), ("n_palette", C.c_int32),
+                ("cx", C.c_void_p), ("cy", C.c_void_p), ("angle", C.c_void_p),
+                ("length", C.c_void_p), ("half_width", C.c_void_p),
+                ("logits", C.c_void_p), ("palette", C.c_void_p)]
+
+
+class ProgramGrad(C.Structure):
+    _fields_ = [("cx", C.c_void_p), ("cy", C.c_void_p), ("angle", C.c_void_p),
+                ("length", C.c_void_p), ("half_width", C.c_void_p),
+                ("logits", C.c_void_p), ("palette", C.c_void_p)]
+
+
+class RenderOpts(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("tau", C.c_float),
+                ("tau_min", C.c_float), ("tau_c", C.c_float), ("eps_floor", C.c_float),
+                ("ckpt_interval", C.c_int32), ("side_slots", C.c_int32)]
+
+
+class AdamOpts(C.Structure):
+    _fields_ = [("lr_centre", C.c_float), ("lr_angle", C.c_float), ("lr_length", C.c_float),
+                ("lr_width", C.c_float), ("lr_logits", C.c_float), ("lr_palette", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("r_lo", C.c_float), ("r_hi", C.c_float), ("l_max", C.c_float),
+                ("step", C.c_int32)]
+
+
+# Every exported symbol of include/tbr.h, with its ctypes signature.
+_vp, _sz, _i32 = C.c_void_p, C.c_size_t, C.c_int32
+SIGNATURES = {
+    "tbr_render_workspace_bytes": (_sz, [_vp, _i32, _i32, _i32]),
+    "tbr_render": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _i32, _vp]),
+    "tbr_tape_records": (_i32, [_vp, _sz, _vp, _i32, _vp, _vp]),
+    "tbr_backward_workspace_bytes": (_sz, [_vp, _i32, _i32]),
+    "tbr_render_backward": (_i32, [_vp, _vp, _vp, _sz, _vp, _vp, _vp, _sz, _vp]),
+    "tbr_fit_workspace_bytes": (_sz, [_vp, _i32, _i32]),
+    "tbr_fit_step": (_i32, [_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "tbr_set_timing_events": (_i32, [C.c_char_p, _vp, _vp]),
+    "tbr_last_error": (C.c_char_p, []),
+    "tbr_version": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load():
+    """Load libtbr.so; raise if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2609_08722_amd.build` (hipcc, gfx950)")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def check(status: int) -> int:
+    if status < 0:
+        raise TbrError(status, load().tbr_last_error().decode())
+    return status

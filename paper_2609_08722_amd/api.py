@@ -1,0 +1,261 @@
+"""Python surface of the HIP renderer: marshalling of torch CUDA tensors into
+the C ABI of include/tbr.h. Every step of the computation runs in the HIP
+kernels of libtbr.so; there is no CPU or PyTorch fallback.
+
+Functions
+  render(prog, opts, mode, tape)       soft / hard forward (Sec. 3, Eq. render)
+  render_backward(prog, opts, tape, g) replay adjoint (Sec. 5.2)
+  TBRRender                            torch.autograd.Function around both
+  FitState.step(target)                one L2 fit step with Adam (Sec. 5.1)
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+GEOM = ("cx", "cy", "angle", "length", "half_width")
+FIELDS = GEOM + ("logits", "palette")
+
+
+@dataclass
+class Opts:
+    """Render options (tbr_render_opts)."""
+    width: int
+    height: int
+    tau: float = 1e-3
+    tau_min: float | None = None      # default 0.7 pixel: 0.7 / width
+    tau_c: float = 0.0
+    eps: float = 1e-3
+    ckpt: int = 256
+    side_slots: int = 16
+
+    def c(self) -> L.RenderOpts:
+        tm = 0.7 / self.width if self.tau_min is None else self.tau_min
+        return L.RenderOpts(int(self.width), int(self.height), float(self.tau), float(tm),
+                            float(self.tau_c), float(self.eps), int(self.ckpt),
+                            int(self.side_slots))
+
+    @property
+    def pixels(self) -> int:
+        return self.width * self.height
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def to_device(arrs: dict, device="cuda") -> dict:
+    """Program dict (numpy or torch) -> contiguous float32 CUDA tensors."""
+    out = {}
+    for k in FIELDS:
+        v = arrs[k]
+        t = v if isinstance(v, torch.Tensor) else torch.from_numpy(np.asarray(v))
+        out[k] = t.to(device=device, dtype=torch.float32).contiguous()
+    return out
+
+
+def _check_prog(prog: dict):
+    n = prog["cx"].numel()
+    k = prog["palette"].numel() // 3
+    for f in FIELDS:
+        t = prog[f]
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError(f"{f} must be a contiguous float32 CUDA tensor")
+    for f in GEOM:
+        if prog[f].numel() != n:
+            raise ValueError(f"{f} has {prog[f].numel()} entries, expected {n}")
+    if prog["logits"].numel() != n * k or prog["palette"].numel() != 3 * k:
+        raise ValueError("logits must be [N, K] and palette [K, 3]")
+    return n, k
+
+
+def c_program(prog: dict) -> L.Program:
+    n, k = _check_prog(prog)
+    return L.Program(n, k, *[_ptr(prog[f]) for f in FIELDS])
+
+
+@dataclass
+class Tape:
+    """Workspace holding the replay tape of one soft render."""
+    ws: torch.Tensor
+    opts: Opts
+    n_strokes: int
+    max_records: int = -1
+    keep: list = field(default_factory=list)
+
+
+def render(prog: dict, opts: Opts, mode: str = "soft", tape: bool = False,
+           check_overflow: bool = True) -> dict:
+    """Forward render. mode: 'soft', 'hard' or 'both'. Returns rgb [H,W,3]
+    (soft if requested), label / owner [H,W] int32 for hard, and the tape."""
+    lib = L.load()
+    cp = c_program(prog)
+    flags = {"soft": L.TBR_SOFT, "hard": L.TBR_HARD, "both": L.TBR_SOFT | L.TBR_HARD}[mode]
+    dev = prog["cx"].device
+    H, W = opts.height, opts.width
+    while True:
+        co = opts.c()
+        nbytes = lib.tbr_render_workspace_bytes(C.byref(co), cp.n_strokes, flags, int(tape))
+        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        rgb = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+        label = owner = None
+        if flags & L.TBR_HARD:
+            label = torch.empty((H, W), dtype=torch.int32, device=dev)
+            owner = torch.empty((H, W), dtype=torch.int32, device=dev)
+        L.check(lib.tbr_render(C.byref(cp), C.byref(co), flags, _ptr(rgb), _ptr(label),
+                               _ptr(owner), _ptr(ws), nbytes, int(tape), _stream()))
+        out = {"rgb": rgb, "label": label, "owner": owner}
+        if not tape:
+            return out
+        t = Tape(ws, opts, cp.n_strokes)
+        if check_overflow:
+            mr = C.c_int32(0)
+            st = lib.tbr_tape_records(_ptr(ws), nbytes, C.byref(co), cp.n_strokes,
+                                      C.byref(mr), _stream())
+            t.max_records = mr.value
+            if st == L.TBR_E_OVERFLOW:
+                opts = Opts(**{**opts.__dict__, "side_slots": max(mr.value, 1)})
+                continue
+            L.check(st)
+        out["tape"] = t
+        return out
+
+
+def render_backward(prog: dict, tape: Tape, grad_rgb: torch.Tensor) -> dict:
+    """Replay adjoint: gradients of sum(grad_rgb * R) w.r.t. every program
+    array (same shapes as the program)."""
+    lib = L.load()
+    cp = c_program(prog)
+    co = tape.opts.c()
+    g = grad_rgb.to(torch.float32).contiguous()
+    if g.numel() != 3 * tape.opts.pixels or not g.is_cuda:
+        raise ValueError("grad_rgb must be a CUDA tensor of H*W*3 values")
+    grads = {f: torch.empty_like(prog[f]) for f in FIELDS}
+    cg = L.ProgramGrad(*[_ptr(grads[f]) for f in FIELDS])
+    nbytes = lib.tbr_backward_workspace_bytes(C.byref(co), cp.n_strokes, cp.n_palette)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=g.device)
+    L.check(lib.tbr_render_backward(C.byref(cp), C.byref(co), _ptr(tape.ws), tape.ws.numel(),
+                                    _ptr(g), C.byref(cg), _ptr(ws), nbytes, _stream()))
+    return grads
+
+
+class TBRRender(torch.autograd.Function):
+    """rgb = R(program) (soft render) with the replay adjoint as backward."""
+
+    @staticmethod
+    def forward(ctx, cx, cy, angle, length, half_width, logits, palette, opts: Opts):
+        prog = {"cx": cx.contiguous(), "cy": cy.contiguous(), "angle": angle.contiguous(),
+                "length": length.contiguous(), "half_width": half_width.contiguous(),
+                "logits": logits.contiguous(), "palette": palette.contiguous()}
+        out = render(prog, opts, "soft", tape=True)
+        ctx.prog = prog
+        ctx.tape = out["tape"]
+        return out["rgb"]
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        g = render_backward(ctx.prog, ctx.tape, grad_rgb)
+        return (g["cx"], g["cy"], g["angle"], g["length"], g["half_width"],
+                g["logits"].view_as(ctx.prog["logits"]), g["palette"].view_as(ctx.prog["palette"]),
+                None)
+
+
+def render_soft_autograd(prog: dict, opts: Opts) -> torch.Tensor:
+    return TBRRender.apply(*[prog[f] for f in FIELDS], opts)
+
+
+@dataclass
+class Adam:
+    """Per-group Adam settings (paper Table hyper step sizes)."""
+    lr_centre: float = 0.012
+    lr_angle: float = 0.015
+    lr_length: float = 0.015
+    lr_width: float = 0.018
+    lr_logits: float = 0.030
+    lr_palette: float = 0.010
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    r_lo: float = 0.002
+    r_hi: float = 0.2
+    l_max: float = 0.3
+
+
+def pack(prog: dict) -> torch.Tensor:
+    return torch.cat([prog[f].reshape(-1) for f in FIELDS]).contiguous()
+
+
+def unpack(vec: torch.Tensor, n: int, k: int) -> dict:
+    out, o = {}, 0
+    for f in GEOM:
+        out[f] = vec[o:o + n]
+        o += n
+    out["logits"] = vec[o:o + n * k].view(n, k)
+    o += n * k
+    out["palette"] = vec[o:o + 3 * k].view(k, 3)
+    return out
+
+
+class FitState:
+    """Device-resident state of the fused fit step (tbr_fit_step)."""
+
+    def __init__(self, prog: dict, opts: Opts, adam: Adam | None = None):
+        prog = to_device(prog) if not isinstance(prog["cx"], torch.Tensor) or not prog["cx"].is_cuda else prog
+        self.n, self.k = _check_prog(prog)
+        self.opts = opts
+        self.adam = adam or Adam()
+        self.params = pack(prog)
+        self.grads = torch.zeros_like(self.params)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.params.device)
+        self.step_index = 0
+        self._alloc()
+
+    def _alloc(self):
+        lib = L.load()
+        co = self.opts.c()
+        self.nbytes = lib.tbr_fit_workspace_bytes(C.byref(co), self.n, self.k)
+        self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.params.device)
+
+    def program(self) -> dict:
+        return unpack(self.params, self.n, self.k)
+
+    def step(self, target: torch.Tensor) -> torch.Tensor:
+        """One fit step; returns the device loss (before the update)."""
+        lib = L.load()
+        self.step_index += 1
+        a = self.adam
+        ao = L.AdamOpts(a.lr_centre, a.lr_angle, a.lr_length, a.lr_width, a.lr_logits,
+                        a.lr_palette, a.beta1, a.beta2, a.eps, a.r_lo, a.r_hi, a.l_max,
+                        self.step_index)
+        co = self.opts.c()
+        t = target.to(torch.float32).contiguous()
+        L.check(lib.tbr_fit_step(self.n, self.k, _ptr(self.params), _ptr(self.grads),
+                                 _ptr(self.m), _ptr(self.v), C.byref(ao), C.byref(co), _ptr(t),
+                                 _ptr(self.loss), _ptr(self.ws), self.nbytes, _stream()))
+        return self.loss
+
+    def tape_records(self) -> int:
+        """Max side-table records of the last step (synchronises); raises
+        TbrError(TBR_E_OVERFLOW) if the capacity was exceeded."""
+        lib = L.load()
+        co = self.opts.c()
+        mr = C.c_int32(0)
+        L.check(lib.tbr_tape_records(_ptr(self.ws), self.nbytes, C.byref(co), self.n,
+                                     C.byref(mr), _stream()))
+        return mr.value
+
+    def grow_side_table(self, slots: int):
+        self.opts = Opts(**{**self.opts.__dict__, "side_slots": int(slots)})
+        self._alloc()

@@ -1,0 +1,399 @@
+// tbr_api.hip -- host side of the C ABI declared in include/tbr.h:
+// argument validation, workspace layout and kernel launches.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "tbr.h"
+#include "tbr_kernels.hpp"
+
+using namespace tbr;
+
+namespace {
+
+thread_local std::string g_err;
+
+tbr_status fail(tbr_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+tbr_status fail(tbr_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+tbr_status check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(TBR_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  return TBR_OK;
+}
+
+// Benchmark timing hook (tbr_set_timing_events).
+thread_local std::string g_timed_kernel;
+thread_local hipEvent_t g_ev_begin = nullptr, g_ev_end = nullptr;
+
+struct Timed {
+  bool on;
+  hipStream_t st;
+  Timed(const char* name, hipStream_t s) : on(g_ev_begin && g_timed_kernel == name), st(s) {
+    if (on) (void)hipEventRecord(g_ev_begin, st);
+  }
+  ~Timed() {
+    if (on) (void)hipEventRecord(g_ev_end, st);
+  }
+};
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+constexpr int kTile = 16;  // pixels per block side (4 waves of 8x8)
+
+int tiles_x(const tbr_render_opts* o) { return (o->width + kTile - 1) / kTile; }
+int tiles_y(const tbr_render_opts* o) { return (o->height + kTile - 1) / kTile; }
+size_t n_tiles(const tbr_render_opts* o) { return (size_t)tiles_x(o) * tiles_y(o); }
+size_t n_pixels(const tbr_render_opts* o) { return (size_t)o->width * o->height; }
+
+int n_ckpt(const tbr_render_opts* o, int n) {
+  if (o->ckpt_interval <= 0 || n <= 1) return 1;
+  return 1 + (n - 1) / o->ckpt_interval;
+}
+
+// Render workspace: [recs][status][tape: nrec | ckpt | side_idx | side_xy]
+struct RenderLayout {
+  size_t recs, status, nrec, ckpt_xy, ckpt_t, side_idx, side_xy, total;
+};
+
+RenderLayout render_layout(const tbr_render_opts* o, int n, bool tape) {
+  RenderLayout L{};
+  size_t off = 0;
+  L.recs = off;
+  off = align_up(off + (size_t)(n > 0 ? n : 1) * sizeof(StrokeRec));
+  L.status = off;
+  off = align_up(off + 64);
+  if (tape) {
+    size_t P = n_pixels(o);
+    L.nrec = off;
+    off = align_up(off + P * sizeof(int32_t));
+    L.ckpt_xy = off;
+    off = align_up(off + (size_t)n_ckpt(o, n) * P * sizeof(double2));
+    L.ckpt_t = off;
+    off = align_up(off + (size_t)n_ckpt(o, n) * P * sizeof(float2));
+    L.side_idx = off;
+    off = align_up(off + (size_t)o->side_slots * P * sizeof(int32_t));
+    L.side_xy = off;
+    off = align_up(off + (size_t)o->side_slots * P * sizeof(double2));
+  }
+  L.total = off;
+  return L;
+}
+
+constexpr int kGroups = 32;  // first-stage groups of the tile sum
+
+struct BackLayout {
+  size_t partial, groups, gcol, pal_terms, total;
+};
+
+BackLayout back_layout(const tbr_render_opts* o, int n, int k) {
+  BackLayout L{};
+  size_t rows8 = (size_t)(n + 1) * 8, off = 0;
+  L.partial = off;
+  off = align_up(off + n_tiles(o) * rows8 * sizeof(float));
+  L.groups = off;
+  off = align_up(off + (size_t)kGroups * rows8 * sizeof(double));
+  L.gcol = off;
+  off = align_up(off + (size_t)(n + 1) * 3 * sizeof(float));
+  L.pal_terms = off;
+  off = align_up(off + (size_t)(n > 0 ? n : 1) * k * 3 * sizeof(float));
+  L.total = off;
+  return L;
+}
+
+struct FitLayout {
+  RenderLayout r;
+  BackLayout b;
+  size_t base_r, base_b, seed, loss_part, grads, total;
+};
+
+size_t packed_len(int n, int k) { return (size_t)5 * n + (size_t)n * k + (size_t)3 * k; }
+
+FitLayout fit_layout(const tbr_render_opts* o, int n, int k) {
+  FitLayout L{};
+  L.r = render_layout(o, n, true);
+  L.b = back_layout(o, n, k);
+  size_t off = 0;
+  L.base_r = off;
+  off = align_up(off + L.r.total);
+  L.base_b = off;
+  off = align_up(off + L.b.total);
+  L.seed = off;
+  off = align_up(off + n_pixels(o) * 3 * sizeof(float));
+  L.loss_part = off;
+  off = align_up(off + n_tiles(o) * sizeof(float));
+  L.grads = off;
+  off = align_up(off + packed_len(n, k) * sizeof(float));
+  L.total = off;
+  return L;
+}
+
+tbr_status check_opts(const tbr_render_opts* o, bool soft, bool tape) {
+  if (!o) return fail(TBR_E_INVALID, "opts is NULL");
+  if (o->width < 1 || o->width > 16384 || o->height < 1 || o->height > 16384)
+    return fail(TBR_E_INVALID, "canvas %dx%d outside 1..16384", o->width, o->height);
+  if (!(o->tau >= 0.f) || !std::isfinite(o->tau)) return fail(TBR_E_INVALID, "tau must be >= 0");
+  if (soft && !(o->tau_min > 0.f)) return fail(TBR_E_INVALID, "tau_min must be > 0 for soft renders");
+  if (!(o->tau_c >= 0.f) || !std::isfinite(o->tau_c)) return fail(TBR_E_INVALID, "tau_c must be >= 0");
+  if (!(o->eps_floor > 0.f) || !std::isfinite(o->eps_floor))
+    return fail(TBR_E_INVALID, "eps_floor must be > 0");
+  if (o->ckpt_interval < 0) return fail(TBR_E_INVALID, "ckpt_interval must be >= 0");
+  if (tape && o->side_slots < 1) return fail(TBR_E_INVALID, "side_slots must be >= 1 with a tape");
+  if (o->side_slots < 0) return fail(TBR_E_INVALID, "side_slots must be >= 0");
+  return TBR_OK;
+}
+
+tbr_status check_prog(const tbr_program* p) {
+  if (!p) return fail(TBR_E_INVALID, "program is NULL");
+  if (p->n_strokes < 0) return fail(TBR_E_INVALID, "n_strokes = %d < 0", p->n_strokes);
+  if (p->n_palette < 1 || p->n_palette > 64)
+    return fail(TBR_E_INVALID, "n_palette = %d outside 1..64", p->n_palette);
+  if (!p->palette) return fail(TBR_E_INVALID, "palette is NULL");
+  if (p->n_strokes > 0 && (!p->cx || !p->cy || !p->angle || !p->length || !p->half_width || !p->logits))
+    return fail(TBR_E_INVALID, "a stroke array is NULL");
+  return TBR_OK;
+}
+
+KProgram kprog(const tbr_program* p) {
+  return KProgram{p->n_strokes, p->n_palette, p->cx, p->cy, p->angle, p->length,
+                  p->half_width, p->logits, p->palette};
+}
+KOpts kopts(const tbr_render_opts* o) { return KOpts{o->tau, o->tau_min, o->tau_c, o->eps_floor}; }
+
+KTape ktape(char* ws, const RenderLayout& L, const tbr_render_opts* o, bool tape) {
+  KTape t{};
+  t.status = reinterpret_cast<int32_t*>(ws + L.status);
+  t.ckpt_interval = o->ckpt_interval;
+  t.side_slots = o->side_slots;
+  if (tape) {
+    t.ckpt_xy = reinterpret_cast<double2*>(ws + L.ckpt_xy);
+    t.ckpt_t = reinterpret_cast<float2*>(ws + L.ckpt_t);
+    t.nrec = reinterpret_cast<int32_t*>(ws + L.nrec);
+    t.side_idx = reinterpret_cast<int32_t*>(ws + L.side_idx);
+    t.side_xy = reinterpret_cast<double2*>(ws + L.side_xy);
+  }
+  return t;
+}
+
+tbr_status launch_prep(const tbr_program* p, const tbr_render_opts* o, StrokeRec* recs,
+                       int32_t* status, hipStream_t st) {
+  int nb = (p->n_strokes + 255) / 256;
+  if (nb < 1) nb = 1;
+  k_stroke_prep<<<nb, 256, 0, st>>>(kprog(p), kopts(o), recs, status);
+  return check_launch("stroke_prep");
+}
+
+tbr_status launch_backward(const tbr_program* p, const tbr_render_opts* o, const char* tape_ws,
+                           const RenderLayout& RL, const float* grad_rgb, const tbr_program_grad* g,
+                           char* ws, const BackLayout& BL, hipStream_t st) {
+  const int n = p->n_strokes;
+  KTape t = ktape(const_cast<char*>(tape_ws), RL, o, true);
+  float* partial = reinterpret_cast<float*>(ws + BL.partial);
+  double* groups = reinterpret_cast<double*>(ws + BL.groups);
+  float* gcol = reinterpret_cast<float*>(ws + BL.gcol);
+  const StrokeRec* recs = reinterpret_cast<const StrokeRec*>(tape_ws + RL.recs);
+  dim3 grid(tiles_x(o), tiles_y(o));
+  {
+    Timed tm("replay", st);
+    k_replay<<<grid, 256, 0, st>>>(recs, n, o->width, o->height, p->palette, grad_rgb, t, partial);
+  }
+  tbr_status s = check_launch("replay");
+  if (s) return s;
+  int rows8 = (n + 1) * 8;
+  int nt = (int)n_tiles(o);
+  int tpg = (nt + kGroups - 1) / kGroups;
+  k_sum_tiles<<<dim3((rows8 + 255) / 256, kGroups), 256, 0, st>>>(partial, rows8, nt, tpg, groups);
+  if ((s = check_launch("sum_tiles"))) return s;
+  KGrad kg{g->cx, g->cy, g->angle, g->length, g->half_width, g->logits, g->palette};
+  float* pal_terms = reinterpret_cast<float*>(ws + BL.pal_terms);
+  k_finalize<<<(n + 1 + 255) / 256, 256, 0, st>>>(groups, kGroups, kprog(p), kopts(o), kg, gcol,
+                                                  pal_terms);
+  if ((s = check_launch("finalize"))) return s;
+  k_palette_grad<<<p->n_palette * 3, 256, 0, st>>>(pal_terms, n, p->n_palette, gcol, g->palette);
+  return check_launch("palette_grad");
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tbr_render_workspace_bytes(const tbr_render_opts* opts, int32_t n_strokes, int32_t mode,
+                                  int32_t with_tape) {
+  if (!opts || n_strokes < 0) return 0;
+  return render_layout(opts, n_strokes, with_tape && (mode & TBR_SOFT)).total;
+}
+
+tbr_status tbr_render(const tbr_program* prog, const tbr_render_opts* opts, int32_t mode,
+                      float* rgb, int32_t* label, int32_t* owner, void* workspace,
+                      size_t workspace_bytes, int32_t with_tape, void* stream) {
+  tbr_status s;
+  if ((s = check_prog(prog))) return s;
+  const bool soft = mode & TBR_SOFT, hard = mode & TBR_HARD;
+  if (!(soft || hard) || (mode & ~(TBR_SOFT | TBR_HARD)))
+    return fail(TBR_E_INVALID, "mode %d is not TBR_SOFT and/or TBR_HARD", mode);
+  if (with_tape && !soft) return fail(TBR_E_INVALID, "a tape needs TBR_SOFT");
+  if ((s = check_opts(opts, soft, with_tape != 0))) return s;
+  if (!workspace) return fail(TBR_E_INVALID, "workspace is NULL");
+  RenderLayout L = render_layout(opts, prog->n_strokes, with_tape != 0);
+  if (workspace_bytes < L.total)
+    return fail(TBR_E_INVALID, "workspace %zu bytes < required %zu", workspace_bytes, L.total);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  StrokeRec* recs = reinterpret_cast<StrokeRec*>(ws + L.recs);
+  KTape t = ktape(ws, L, opts, with_tape != 0);
+  if ((s = launch_prep(prog, opts, recs, t.status, st))) return s;
+  dim3 grid(tiles_x(opts), tiles_y(opts));
+  if (soft) {
+    {
+      Timed tm("trace_soft", st);
+      k_trace_soft<<<grid, 256, 0, st>>>(recs, prog->n_strokes, opts->width, opts->height,
+                                         prog->palette, rgb, t, KSeed{nullptr, nullptr, nullptr});
+    }
+    if ((s = check_launch("trace_soft"))) return s;
+  }
+  if (hard && (label || owner || (!soft && rgb))) {
+    {
+      Timed tm("trace_hard", st);
+      k_trace_hard<<<grid, 256, 0, st>>>(recs, prog->n_strokes, opts->width, opts->height,
+                                         prog->palette, soft ? nullptr : rgb, label, owner);
+    }
+    if ((s = check_launch("trace_hard"))) return s;
+  }
+  return TBR_OK;
+}
+
+tbr_status tbr_tape_records(const void* workspace, size_t workspace_bytes,
+                            const tbr_render_opts* opts, int32_t n_strokes,
+                            int32_t* max_records, void* stream) {
+  if (!workspace || !opts || !max_records || n_strokes < 0)
+    return fail(TBR_E_INVALID, "null argument");
+  RenderLayout L = render_layout(opts, n_strokes, false);
+  if (workspace_bytes < L.total) return fail(TBR_E_INVALID, "workspace too small");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int32_t v = 0;
+  hipError_t e = hipMemcpyAsync(&v, static_cast<const char*>(workspace) + L.status, sizeof v,
+                                hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(TBR_E_DEVICE, "tape_records: %s", hipGetErrorString(e));
+  *max_records = v;
+  if (v > opts->side_slots)
+    return fail(TBR_E_OVERFLOW, "side table needs %d slots per pixel, has %d", v, opts->side_slots);
+  return TBR_OK;
+}
+
+size_t tbr_backward_workspace_bytes(const tbr_render_opts* opts, int32_t n_strokes,
+                                    int32_t n_palette) {
+  if (!opts || n_strokes < 0 || n_palette < 1) return 0;
+  return back_layout(opts, n_strokes, n_palette).total;
+}
+
+tbr_status tbr_render_backward(const tbr_program* prog, const tbr_render_opts* opts,
+                               const void* tape_ws, size_t tape_bytes, const float* grad_rgb,
+                               const tbr_program_grad* grad, void* workspace,
+                               size_t workspace_bytes, void* stream) {
+  tbr_status s;
+  if ((s = check_prog(prog))) return s;
+  if ((s = check_opts(opts, true, true))) return s;
+  if (!tape_ws || !grad_rgb || !grad || !workspace) return fail(TBR_E_INVALID, "null argument");
+  if (!grad->palette || (prog->n_strokes > 0 && (!grad->cx || !grad->cy || !grad->angle ||
+                                                 !grad->length || !grad->half_width || !grad->logits)))
+    return fail(TBR_E_INVALID, "a gradient array is NULL");
+  RenderLayout RL = render_layout(opts, prog->n_strokes, true);
+  if (tape_bytes < RL.total) return fail(TBR_E_INVALID, "tape %zu bytes < %zu", tape_bytes, RL.total);
+  BackLayout BL = back_layout(opts, prog->n_strokes, prog->n_palette);
+  if (workspace_bytes < BL.total)
+    return fail(TBR_E_INVALID, "workspace %zu bytes < required %zu", workspace_bytes, BL.total);
+  return launch_backward(prog, opts, static_cast<const char*>(tape_ws), RL, grad_rgb, grad,
+                         static_cast<char*>(workspace), BL, reinterpret_cast<hipStream_t>(stream));
+}
+
+size_t tbr_fit_workspace_bytes(const tbr_render_opts* opts, int32_t n_strokes, int32_t n_palette) {
+  if (!opts || n_strokes < 0 || n_palette < 1) return 0;
+  return fit_layout(opts, n_strokes, n_palette).total;
+}
+
+tbr_status tbr_fit_step(int32_t n_strokes, int32_t n_palette, float* params, float* grads,
+                        float* adam_m, float* adam_v, const tbr_adam_opts* adam,
+                        const tbr_render_opts* opts, const float* target_rgb, float* loss,
+                        void* workspace, size_t workspace_bytes, void* stream) {
+  tbr_status s;
+  if (n_strokes < 0 || n_palette < 1 || n_palette > 64)
+    return fail(TBR_E_INVALID, "n_strokes %d / n_palette %d out of range", n_strokes, n_palette);
+  if (!params || !adam_m || !adam_v || !adam || !target_rgb || !loss || !workspace)
+    return fail(TBR_E_INVALID, "null argument");
+  if ((s = check_opts(opts, true, true))) return s;
+  if (adam->step < 1) return fail(TBR_E_INVALID, "adam step must be >= 1");
+  if (!(adam->beta1 >= 0.f && adam->beta1 < 1.f && adam->beta2 >= 0.f && adam->beta2 < 1.f &&
+        adam->eps > 0.f && adam->r_lo > 0.f && adam->r_hi >= adam->r_lo && adam->l_max >= 0.f))
+    return fail(TBR_E_INVALID, "bad Adam settings");
+  FitLayout FL = fit_layout(opts, n_strokes, n_palette);
+  if (workspace_bytes < FL.total)
+    return fail(TBR_E_INVALID, "workspace %zu bytes < required %zu", workspace_bytes, FL.total);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  char* rws = ws + FL.base_r;
+  char* bws = ws + FL.base_b;
+  const int N = n_strokes, K = n_palette;
+  float* g = grads ? grads : reinterpret_cast<float*>(ws + FL.grads);
+  tbr_program prog{N, K, params, params + N, params + 2 * N, params + 3 * N, params + 4 * N,
+                   params + 5 * N, params + 5 * N + (size_t)N * K};
+  tbr_program_grad pg{g, g + N, g + 2 * N, g + 3 * N, g + 4 * N, g + 5 * N,
+                      g + 5 * N + (size_t)N * K};
+  StrokeRec* recs = reinterpret_cast<StrokeRec*>(rws + FL.r.recs);
+  KTape t = ktape(rws, FL.r, opts, true);
+  if ((s = launch_prep(&prog, opts, recs, t.status, st))) return s;
+  float* seed = reinterpret_cast<float*>(ws + FL.seed);
+  float* lpart = reinterpret_cast<float*>(ws + FL.loss_part);
+  dim3 grid(tiles_x(opts), tiles_y(opts));
+  {
+    Timed tm("trace_soft", st);
+    k_trace_soft<<<grid, 256, 0, st>>>(recs, N, opts->width, opts->height, prog.palette, nullptr,
+                                       t, KSeed{target_rgb, seed, lpart});
+  }
+  if ((s = check_launch("trace_soft"))) return s;
+  k_loss_final<<<1, 256, 0, st>>>(lpart, (int)n_tiles(opts), 1.0f / (3.0f * (float)n_pixels(opts)),
+                                  loss);
+  if ((s = check_launch("loss_final"))) return s;
+  if ((s = launch_backward(&prog, opts, rws, FL.r, seed, &pg, bws, FL.b, st))) return s;
+  KAdam a{adam->lr_centre, adam->lr_angle, adam->lr_length, adam->lr_width, adam->lr_logits,
+          adam->lr_palette, adam->beta1, adam->beta2, adam->eps,
+          (float)(1.0 - std::pow((double)adam->beta1, adam->step)),
+          (float)(1.0 - std::pow((double)adam->beta2, adam->step)),
+          adam->r_lo, adam->r_hi, adam->l_max};
+  int total = (int)packed_len(N, K);
+  k_adam<<<(total + 255) / 256, 256, 0, st>>>(params, g, adam_m, adam_v, N, K, a);
+  return check_launch("adam");
+}
+
+tbr_status tbr_set_timing_events(const char* kernel, void* begin, void* end) {
+  if (!kernel) {
+    g_timed_kernel.clear();
+    g_ev_begin = g_ev_end = nullptr;
+    return TBR_OK;
+  }
+  if (!begin || !end) return fail(TBR_E_INVALID, "timing events are NULL");
+  g_timed_kernel = kernel;
+  g_ev_begin = reinterpret_cast<hipEvent_t>(begin);
+  g_ev_end = reinterpret_cast<hipEvent_t>(end);
+  return TBR_OK;
+}
+
+const char* tbr_last_error(void) { return g_err.c_str(); }
+
+const char* tbr_version(void) { return "tbr 0.1.0 (gfx950)"; }
+
+}  // extern "C"

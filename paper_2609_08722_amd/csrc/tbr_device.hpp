@@ -1,0 +1,329 @@
+// tbr_device.hpp -- per-lane FP32 arithmetic of the capsule transport.
+//
+// One pixel per lane. Stroke constants arrive as a wave-uniform 64-byte
+// record (scalar loads); everything else lives in VGPRs. All maps are the
+// closed forms of Sec. 4 of the paper (TBR, arxiv 2609.08722):
+//   distance sigma to the segment, Steiner area A_l(s) = 2 l s + pi s^2 and
+//   perimeter P_l(s) = 2 l + 2 pi s (Eq. steiner), the centred arclength
+//   fraction w (Prop. centred arclength), the backward root (Eq. back) with
+//   the implemented floor C >= (eps r)^2 (Sec. 5.2), the forward root
+//   (Eq. fwd), and the soft coverage of Eq. (relax) clamped at 1 - 1e-7.
+//
+// Transcendentals: raw v_sqrt/v_rcp/v_exp (about 1 ulp) plus the
+// first-quadrant atan / sin / cos polynomials of minimax_coeffs.h (Remez
+// fits, about 1e-7 absolute in FP32). Every branch of the chart is written
+// branch-free: on the flank of the capsule the cap angle is exactly 0, its
+// sine 0 and cosine 1, so the cap formulas reduce to the flank ones.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "minimax_coeffs.h"
+
+namespace tbr {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kTwoPi = 6.28318530717958647692f;
+constexpr float kHalfPi = 1.57079632679489661923f;
+constexpr float kLog2e = 1.44269504088896340736f;
+// alpha = e^z / (1 + e^z) <= 1 - 1e-7   <=>   e^z <= (1 - 1e-7) / 1e-7
+constexpr float kEzMax = 9999999.0f;
+
+// Per-stroke constants, prepared once per launch (64 bytes, 16 words).
+struct __align__(16) StrokeRec {
+  float mx, my;     // centre m
+  float ce, se;     // direction e = (cos phi, sin phi)
+  float hl, ell;    // half-length l/2 and length l = |L|
+  float r, ar;      // half-width r and inserted area A_l(r)
+  float inv_wd;     // 1 / max(tau r, tau_min)
+  float floor_c;    // (eps r)^2
+  float dfloor_dr;  // d (eps r)^2 / dr = 2 eps^2 r
+  float dwd_dr;     // d max(tau r, tau_min) / dr: tau or 0
+  float cr, cg, cb; // colour c_i = softmax(z_i / tau_c) P (or P[argmax])
+  int label;        // argmax_k z_ik (hard colour index)
+};
+static_assert(sizeof(StrokeRec) == 64, "stroke record must be 64 bytes");
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float hw_exp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
+
+// atan(a) for a in [0, 1].
+__device__ __forceinline__ float atan01(float a) {
+  float u = a * a;
+  float p = kAtan[8];
+  p = fmaf(p, u, kAtan[7]);
+  p = fmaf(p, u, kAtan[6]);
+  p = fmaf(p, u, kAtan[5]);
+  p = fmaf(p, u, kAtan[4]);
+  p = fmaf(p, u, kAtan[3]);
+  p = fmaf(p, u, kAtan[2]);
+  p = fmaf(p, u, kAtan[1]);
+  p = fmaf(p, u, kAtan[0]);
+  return a * p;
+}
+
+// atan2(y, x) for y, x >= 0 (first quadrant); 0 at the origin.
+__device__ __forceinline__ float atan2_q1(float y, float x) {
+  float hi = fmaxf(x, y), lo = fminf(x, y);
+  float a = hi > 0.f ? lo * rcp(hi) : 0.f;
+  float t = atan01(a);
+  return y > x ? kHalfPi - t : t;
+}
+
+// Chart of a point w.r.t. one stroke: local coordinates, distance to the
+// segment, cap angle and centred arclength fraction folded into the first
+// quadrant (the reflections of Prop. centred arclength unfold it again).
+// The point is held in FP64; its offset from the stroke centre is rounded to
+// FP32 once, and everything after that is FP32.
+struct Chart {
+  float s, h;      // signed coordinates along e and along n = (-se, ce)
+  float sgs, sgh;  // their signs, +1 at 0
+  float S, H;      // |s|, |h|
+  float E;         // overshoot past the segment end, max(S - l/2, 0)
+  float sig;       // distance to the segment
+  float th;        // cap angle measured from the normal; 0 on the flank
+  float sn, cs;    // sin / cos of th (E / sig, H / sig)
+  float per;       // P_l(sigma)
+  float w;         // arclength fraction from the flank midpoint, [0, 1/4]
+};
+
+__device__ __forceinline__ Chart chart(double x, double y, const StrokeRec& g) {
+  Chart c;
+  float dx = (float)(x - (double)g.mx), dy = (float)(y - (double)g.my);
+  c.s = fmaf(dx, g.ce, dy * g.se);
+  c.h = fmaf(dy, g.ce, -(dx * g.se));
+  c.sgs = c.s < 0.f ? -1.f : 1.f;
+  c.sgh = c.h < 0.f ? -1.f : 1.f;
+  c.S = fabsf(c.s);
+  c.H = fabsf(c.h);
+  c.E = fmaxf(c.S - g.hl, 0.f);
+  c.sig = hw_sqrt(fmaf(c.H, c.H, c.E * c.E));
+  c.th = atan2_q1(c.E, c.H);
+  float inv_sig = c.sig > 0.f ? rcp(c.sig) : 0.f;
+  c.sn = c.E * inv_sig;
+  c.cs = c.sig > 0.f ? c.H * inv_sig : 1.f;
+  float t = fmaf(c.sig, c.th, fminf(c.S, g.hl));  // arclength from the flank midpoint
+  c.per = fmaf(kTwoPi, c.sig, g.ell + g.ell);      // P_l(sigma)
+  c.w = c.per > 0.f ? t * rcp(c.per) : 0.f;        // drop centre: w := 0
+  return c;
+}
+
+// Distance whose parallel set has area Q, cancellation-free root of
+// pi s^2 + 2 l s = Q (Eq. back / Eq. fwd).
+__device__ __forceinline__ float area_to_dist(float q, const StrokeRec& g) {
+  return q * rcp(g.ell + hw_sqrt(fmaf(g.ell, g.ell, kPi * q)));
+}
+
+// Backward numerator C = A(sigma') - A(r), factored (Eq. back).
+__device__ __forceinline__ float back_area(float sig, const StrokeRec& g) {
+  return (sig - g.r) * fmaf(kPi, sig + g.r, g.ell + g.ell);
+}
+
+// Forward numerator B = A(sigma) + A(r) (Eq. fwd).
+__device__ __forceinline__ float fwd_area(float sig, const StrokeRec& g) {
+  return fmaf(sig, fmaf(kPi, sig, g.ell + g.ell), g.ar);
+}
+
+// sin(d) and cos(d) - 1 for d in [-pi/2, pi/2] (odd / even polynomials).
+__device__ __forceinline__ void sincosm1(float d, float& s, float& cm1) {
+  float u = d * d;
+  float ps = kSin[5];
+  ps = fmaf(ps, u, kSin[4]);
+  ps = fmaf(ps, u, kSin[3]);
+  ps = fmaf(ps, u, kSin[2]);
+  ps = fmaf(ps, u, kSin[1]);
+  ps = fmaf(ps, u, kSin[0]);
+  s = d * ps;
+  float pc = kCos[5];
+  pc = fmaf(pc, u, kCos[4]);
+  pc = fmaf(pc, u, kCos[3]);
+  pc = fmaf(pc, u, kCos[2]);
+  pc = fmaf(pc, u, kCos[1]);
+  cm1 = u * pc;  // kCos[0] == 1
+}
+
+// One application of the insertion map or its inverse to a charted point,
+// as a DISPLACEMENT in the folded local frame. The new point is the one on
+// the level curve at distance sig_o with the same fraction w. Writing the
+// folded position as F(t, s) = (t - s (th - sin th), s - s (1 - cos th)),
+// th = max(t - l/2, 0) / s, t = w P_l(s), the displacement is assembled from
+//   dsig = sig_o - sig = (A(sig_o) - A(sig)) / (2 l + pi (sig + sig_o)),
+//     where A(sig_o) - A(sig) = -A(r) (psi), +A(r) (Phi) or the floor term,
+//   dt   = 2 pi w dsig,
+//   dth  = dsig l (pi - 2 th) / (P_l(sig) sig_o)   (cap to cap; the identity
+//          2 pi w - th = l (pi - 2 th) / P_l(sig) removes the cancellation),
+//   and the rotation of (sin th, cos th) by dth,
+// so no term of the size of the distance itself is rounded: the FP64 state
+// then advances by a small FP32 increment.
+struct Move {
+  float sig_o;           // distance of the new point
+  float dS, dH;          // folded displacement
+  float th_o, sn_o, cs_o;  // cap angle of the new point and its sin / cos
+  bool floored;          // psi only: the floor C >= (eps r)^2 bound
+};
+
+__device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, bool backward) {
+  Move m;
+  const float two_ell = g.ell + g.ell;
+  // psi: Eq. (back) with the implemented floor; Phi: Eq. (fwd)
+  float cq = back_area(c.sig, g);
+  m.floored = backward && cq < g.floor_c;
+  float q = backward ? fmaxf(cq, g.floor_c) : fwd_area(c.sig, g);
+  float num = backward ? (m.floored ? g.floor_c - c.sig * fmaf(kPi, c.sig, two_ell) : -g.ar) : g.ar;
+  m.sig_o = area_to_dist(q, g);
+  float dsig = num * rcp(fmaf(kPi, c.sig + m.sig_o, two_ell));
+  float dt = kTwoPi * c.w * dsig;
+  float t_o = c.w * fmaf(kTwoPi, m.sig_o, two_ell);
+  float th_o = fminf(fmaxf(t_o - g.hl, 0.f) * rcp(m.sig_o), kHalfPi);
+  const bool cap_in = c.th > 0.f, cap_out = th_o > 0.f;
+  float dth_cc = dsig * g.ell * (kPi - 2.f * c.th) * rcp(c.per * m.sig_o);
+  float dth = (cap_in && cap_out) ? dth_cc : th_o - c.th;
+  float sd, cdm1;
+  sincosm1(dth, sd, cdm1);
+  float dsin = fmaf(c.sn, cdm1, c.cs * sd);
+  float dcos = fmaf(c.cs, cdm1, -(c.sn * sd));
+  m.sn_o = c.sn + dsin;
+  m.cs_o = c.cs + dcos;
+  m.th_o = (cap_in && cap_out) ? c.th + dth : th_o;
+  float extra = (cap_in && cap_out) ? 0.f : dt - dsig * th_o - c.sig * dth;
+  m.dS = fmaf(dsig, m.sn_o, fmaf(c.sig, dsin, extra));
+  m.dH = fmaf(dsig, m.cs_o, c.sig * dcos);
+  return m;
+}
+
+// Apply a folded displacement to the FP64 state.
+__device__ __forceinline__ void advance(double& x, double& y, const Chart& c, const Move& m,
+                                        const StrokeRec& g) {
+  float a = c.sgs * m.dS, b = c.sgh * m.dH;
+  x += (double)fmaf(a, g.ce, -(b * g.se));
+  y += (double)fmaf(a, g.se, b * g.ce);
+}
+
+// Soft coverage alpha = sigmoid((r - sigma) / wd) with alpha <= 1 - 1e-7,
+// returned with q = 1 - alpha and 1 / q = 1 + e^z (exact identities of the
+// logistic function, so no cancellation in 1 - alpha).
+struct Cover {
+  float z, alpha, q, inv_q;
+  bool clamped;
+};
+
+__device__ __forceinline__ Cover cover(float sig, const StrokeRec& g) {
+  Cover v;
+  v.z = (g.r - sig) * g.inv_wd;
+  float ez = hw_exp(v.z);
+  v.clamped = !(ez < kEzMax);
+  ez = v.clamped ? kEzMax : ez;
+  v.inv_q = 1.f + ez;
+  v.q = rcp(v.inv_q);
+  v.alpha = ez * v.q;
+  return v;
+}
+
+// Transmittance T = Tm * 2^Te with Tm in [0.5, 1): no underflow however many
+// deposits a trajectory crosses (the paper carries log T for the same reason).
+__device__ __forceinline__ void renorm(float& tm, int& te) {
+  te += __builtin_amdgcn_frexp_expf(tm);
+  tm = __builtin_amdgcn_frexp_mantf(tm);
+}
+__device__ __forceinline__ float trans_value(float tm, int te) {
+  return __builtin_amdgcn_ldexpf(tm, te);
+}
+
+// Vector-Jacobian product of one stroke step (Eq. adjstep, Eq. adjparam):
+// given gx, gy = lambda^x_{i-1} (adjoint of the map's output psi_i(x_i))
+// and mu = adjoint of alpha_i, return lambda^x_i and the stroke's
+// contributions d/d(m_x, m_y, phi, l, r). The map is differentiated in
+// reverse through: local frame, distance, fraction, area root, and the
+// reconstruction at the new distance; coverage enters through sigma'.
+//
+// Inputs describe the map at its input point x_i ("in") and output point
+// x_{i-1} ("out"), as produced by either direction of the map.
+struct VjpIn {
+  // input point x_i
+  float s, h, sgs, sgh;  // signed local coordinates and signs
+  float sig;             // sigma' = distance of x_i
+  float th, sn, cs;      // cap angle of x_i and its sin / cos (0, 0, 1 on the flank)
+  float w;               // centred arclength fraction (common to both points)
+  // output point x_{i-1}
+  float Sp, Hp;          // folded local coordinates
+  float rho;             // distance of x_{i-1}
+  float th_o, sn_o, cs_o;
+  bool floored;          // the floor C >= (eps r)^2 bound at x_i
+  // coverage at x_i
+  float z, alpha, q;
+  bool clamped;
+};
+
+struct VjpOut {
+  float gx, gy;                          // lambda^x_i
+  float gmx, gmy, gphi, gell, gr;        // stroke contributions
+};
+
+__device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, float lx,
+                                           float ly, float mu) {
+  VjpOut o;
+  const float two_ell = g.ell + g.ell;
+  // out = m + sgs S' e + sgh H' n
+  float ge = fmaf(lx, g.ce, ly * g.se);
+  float gn = fmaf(ly, g.ce, -(lx * g.se));
+  float sbp = v.sgs * ge;  // adjoint of S'
+  float hbp = v.sgh * gn;  // adjoint of H'
+  o.gmx = lx;
+  o.gmy = ly;
+  o.gphi = fmaf(v.sgs * v.Sp, gn, -(v.sgh * v.Hp * ge));
+  // S' = min(t', l/2) + rho sin th', H' = rho cos th', th' = (t' - l/2) / rho
+  float inv_rho = rcp(v.rho);
+  float thb = v.rho * fmaf(sbp, v.cs_o, -(hbp * v.sn_o));
+  float tpb = thb * inv_rho;
+  float rhob = fmaf(sbp, v.sn_o, hbp * v.cs_o) - tpb * v.th_o;
+  float hlb = sbp - tpb;
+  // t' = w P_l(rho)
+  float p0 = fmaf(kTwoPi, v.rho, two_ell);
+  float wb = tpb * p0;
+  rhob = fmaf(kTwoPi * v.w, tpb, rhob);
+  float ellb = 2.f * v.w * tpb;
+  // rho = A_l^{-1}(C): dC = P_l(rho) drho + 2 rho dl
+  float cb = rhob * rcp(p0);
+  ellb = fmaf(-2.f * v.rho, cb, ellb);
+  // C = A_l(sigma') - A_l(r), or the floor (eps r)^2
+  float p1 = fmaf(kTwoPi, v.sig, two_ell);
+  float pr = fmaf(kTwoPi, g.r, two_ell);
+  float sigb = v.floored ? 0.f : cb * p1;
+  o.gr = v.floored ? cb * g.dfloor_dr : -(cb * pr);
+  ellb = v.floored ? ellb : fmaf(2.f * (v.sig - g.r), cb, ellb);
+  // w = t / P_l(sigma')
+  float inv_p1 = p1 > 0.f ? rcp(p1) : 0.f;
+  float tb = wb * inv_p1;
+  sigb = fmaf(-kTwoPi * v.w, tb, sigb);
+  ellb = fmaf(-2.f * v.w, tb, ellb);
+  // t = min(S, l/2) + sigma' th, th = atan2(E, H), E = S - l/2 (cap form,
+  // exact on the flank too since th = 0 there)
+  hlb += tb;
+  sigb = fmaf(v.th, tb, sigb);
+  float eb = tb * v.cs;
+  float hb = -(tb * v.sn);
+  // coverage: z = (r - sigma') / wd
+  float zb = v.clamped ? 0.f : mu * v.alpha * v.q;
+  float zw = zb * g.inv_wd;
+  sigb -= zw;
+  o.gr = fmaf(zw, fmaf(-v.z, g.dwd_dr, 1.f), o.gr);
+  // sigma' = sqrt(H^2 + E^2)
+  hb = fmaf(sigb, v.cs, hb);
+  eb = fmaf(sigb, v.sn, eb);
+  // E = S - l/2
+  float sb = eb;
+  hlb -= eb;
+  // S = |s|, H = |h|; s = d.e, h = d.n, d = x - m
+  float ssb = v.sgs * sb, shb = v.sgh * hb;
+  o.gx = fmaf(ssb, g.ce, -(shb * g.se));
+  o.gy = fmaf(ssb, g.se, shb * g.ce);
+  o.gmx -= o.gx;
+  o.gmy -= o.gy;
+  o.gphi = fmaf(ssb, v.h, fmaf(-shb, v.s, o.gphi));
+  o.gell = fmaf(0.5f, hlb, ellb);
+  return o;
+}
+
+}  // namespace tbr

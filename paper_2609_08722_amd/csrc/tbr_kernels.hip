@@ -1,0 +1,594 @@
+// tbr_kernels.hip -- HIP kernels for gfx950 (CDNA4), wave64, FP32 VALU.
+//
+// Pixel layout: a block of 256 threads is 4 waves; each wave owns an 8x8
+// pixel tile (lane l -> (l & 7, l >> 3)), the block a 16x16 tile. Pixel
+// centres are ((j + .5) / W, (i + .5) / H), row-major. Stroke records are
+// read with wave-uniform addresses (scalar loads into SGPRs); no stroke data
+// is staged through LDS in the trace kernels.
+//
+// Paper references (TBR, arxiv 2609.08722): Eq. chain and Eq. render
+// (Sec. 3), the operator (Sec. 4), Eq. relax (Sec. 5.1), Eq. state, the
+// regeneration Eqs. rpos / rT, the floor and record rule, log-space
+// transmittance with the alpha clamp, periodic checkpoints, Eq. adjstep and
+// Eq. adjparam (Sec. 5.2).
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tbr_device.hpp"
+#include "tbr_kernels.hpp"
+
+namespace tbr {
+
+// ---------------------------------------------------------------------------
+// Stroke preparation: one thread per stroke.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+    k_stroke_prep(KProgram p, KOpts o, StrokeRec* __restrict__ out, int32_t* __restrict__ status) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && status) *status = 0;  // tape record high-water mark of this launch
+  if (i >= p.n) return;
+  StrokeRec g;
+  g.mx = p.cx[i];
+  g.my = p.cy[i];
+  float phi = p.angle[i];
+  g.ce = cosf(phi);
+  g.se = sinf(phi);
+  float ell = fabsf(p.length[i]);
+  g.ell = ell;
+  g.hl = 0.5f * ell;
+  float r = p.half_width[i];
+  g.r = r;
+  g.ar = r * fmaf(kPi, r, ell + ell);
+  float tr = o.tau * r;
+  bool rel = tr > o.tau_min;
+  float wd = rel ? tr : o.tau_min;
+  g.inv_wd = 1.0f / wd;
+  g.dwd_dr = rel ? o.tau : 0.f;
+  float er = o.eps * r;
+  g.floor_c = er * er;
+  g.dfloor_dr = 2.f * o.eps * er;
+  // colour: softmax(z / tau_c) P, or P[argmax z] when tau_c == 0
+  const float* z = p.logits + (size_t)i * p.k;
+  int best = 0;
+  float zmax = z[0];
+  for (int j = 1; j < p.k; ++j)
+    if (z[j] > zmax) {
+      zmax = z[j];
+      best = j;
+    }
+  g.label = best;
+  float cr = 0.f, cg = 0.f, cb = 0.f;
+  if (o.tau_c > 0.f) {
+    float inv_tc = 1.0f / o.tau_c, tot = 0.f;
+    for (int j = 0; j < p.k; ++j) tot += expf((z[j] - zmax) * inv_tc);
+    float inv_tot = 1.0f / tot;
+    for (int j = 0; j < p.k; ++j) {
+      float s = expf((z[j] - zmax) * inv_tc) * inv_tot;
+      cr = fmaf(s, p.palette[3 * j + 0], cr);
+      cg = fmaf(s, p.palette[3 * j + 1], cg);
+      cb = fmaf(s, p.palette[3 * j + 2], cb);
+    }
+  } else {
+    cr = p.palette[3 * best + 0];
+    cg = p.palette[3 * best + 1];
+    cb = p.palette[3 * best + 2];
+  }
+  g.cr = cr;
+  g.cg = cg;
+  g.cb = cb;
+  out[i] = g;
+}
+
+// Wave-uniform load of a stroke record (the index is uniform, so the
+// compiler issues scalar loads).
+__device__ __forceinline__ StrokeRec load_rec(const StrokeRec* __restrict__ recs, int i) {
+  i = __builtin_amdgcn_readfirstlane(i);
+  return recs[i];
+}
+
+struct PixelId {
+  int px, py;
+  bool active;
+  int p;  // flat index (clamped inside the canvas for inactive lanes)
+};
+
+__device__ __forceinline__ PixelId pixel_of_thread(int width, int height) {
+  PixelId id;
+  int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  id.px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
+  id.py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
+  id.active = id.px < width && id.py < height;
+  int cx = min(id.px, width - 1), cy = min(id.py, height - 1);
+  id.p = cy * width + cx;
+  return id;
+}
+
+// ---------------------------------------------------------------------------
+// Soft forward trace (Eq. chain + Eq. render with Eq. relax), optional tape.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+    k_trace_soft(const StrokeRec* __restrict__ recs, int n, int width, int height,
+                 const float* __restrict__ palette, float* __restrict__ rgb, KTape tape, KSeed seed) {
+  PixelId id = pixel_of_thread(width, height);
+  const float bgr = palette[0], bgg = palette[1], bgb = palette[2];  // c_0 = P[0]
+  const int P = width * height;
+  double x = (id.px + 0.5) / (double)width;
+  double y = (id.py + 0.5) / (double)height;
+  float cr = 0.f, cg = 0.f, cb = 0.f;
+  float tm = 1.0f;
+  int te = 0;
+  int nrec = 0;
+  const bool write_tape = tape.ckpt_xy != nullptr && id.active;
+  const int k = tape.ckpt_interval;
+  for (int i = n - 1; i >= 0; --i) {
+    const StrokeRec g = load_rec(recs, i);
+    // checkpoint of state x_{i+1} (input of stroke i), every k states
+    if (write_tape && k > 0 && ((i + 1) % k) == 0 && (i + 1) < n) {
+      size_t o = (size_t)((i + 1) / k) * P + id.p;
+      tape.ckpt_xy[o] = make_double2(x, y);
+      tape.ckpt_t[o] = make_float2(tm, (float)te);
+    }
+    Chart c = chart(x, y, g);
+    Cover v = cover(c.sig, g);
+    float t = trans_value(tm, te);
+    float ta = t * v.alpha;
+    cr = fmaf(ta, g.cr, cr);
+    cg = fmaf(ta, g.cg, cg);
+    cb = fmaf(ta, g.cb, cb);
+    tm *= v.q;
+    renorm(tm, te);
+    // backward map with the implemented floor; record where it binds
+    Move mv = displace(c, g, true);
+    if (mv.floored) {
+      if (write_tape && nrec < tape.side_slots) {
+        size_t o = (size_t)nrec * P + id.p;
+        tape.side_idx[o] = i;
+        tape.side_xy[o] = make_double2(x, y);
+      }
+      ++nrec;
+    }
+    advance(x, y, c, mv, g);
+  }
+  float t = trans_value(tm, te);
+  cr = fmaf(t, bgr, cr);
+  cg = fmaf(t, bgg, cg);
+  cb = fmaf(t, bgb, cb);
+  if (id.active && rgb) {
+    rgb[3 * (size_t)id.p + 0] = cr;
+    rgb[3 * (size_t)id.p + 1] = cg;
+    rgb[3 * (size_t)id.p + 2] = cb;
+  }
+  if (write_tape) {  // state x_0
+    tape.ckpt_xy[id.p] = make_double2(x, y);
+    tape.ckpt_t[id.p] = make_float2(tm, (float)te);
+    tape.nrec[id.p] = nrec;
+  }
+  // L2 seed (fit step): lambda^C_0 = dL/dR = 2 (R - I*) / (3P), loss partials
+  if (seed.target) {
+    float sq = 0.f;
+    if (id.active) {
+      float dr = cr - seed.target[3 * (size_t)id.p + 0];
+      float dg = cg - seed.target[3 * (size_t)id.p + 1];
+      float db = cb - seed.target[3 * (size_t)id.p + 2];
+      float sc = 2.0f / (3.0f * (float)P);
+      seed.grad_rgb[3 * (size_t)id.p + 0] = sc * dr;
+      seed.grad_rgb[3 * (size_t)id.p + 1] = sc * dg;
+      seed.grad_rgb[3 * (size_t)id.p + 2] = sc * db;
+      sq = fmaf(dr, dr, fmaf(dg, dg, db * db));
+    }
+    // fixed-order block sum of squared errors
+    __shared__ float red[256];
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) seed.loss_part[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+  }
+  if (tape.status) {
+    // max record count over the wave, one atomic per wave
+    int m = id.active ? nrec : 0;
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0 && tape.status) atomicMax(tape.status, m);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Hard trace: first footprint hit going N -> 1; lanes retire on a hit and
+// the wave leaves the stroke loop once every lane has retired (ballot).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+    k_trace_hard(const StrokeRec* __restrict__ recs, int n, int width, int height,
+                 const float* __restrict__ palette, float* __restrict__ rgb,
+                 int32_t* __restrict__ label, int32_t* __restrict__ owner) {
+  PixelId id = pixel_of_thread(width, height);
+  double x = (id.px + 0.5) / (double)width;
+  double y = (id.py + 0.5) / (double)height;
+  bool done = !id.active;
+  int own = -1, lab = 0;
+  for (int i = n - 1; i >= 0; --i) {
+    if (__all(done)) break;
+    const StrokeRec g = load_rec(recs, i);
+    if (!done) {
+      Chart c = chart(x, y, g);
+      if (c.sig <= g.r) {  // closed footprint
+        done = true;
+        own = i;
+        lab = g.label;
+      } else {
+        advance(x, y, c, displace(c, g, true), g);
+      }
+    }
+  }
+  if (id.active) {
+    if (owner) owner[id.p] = own;
+    if (label) label[id.p] = lab;
+    if (rgb) {
+      rgb[3 * (size_t)id.p + 0] = palette[3 * lab + 0];
+      rgb[3 * (size_t)id.p + 1] = palette[3 * lab + 1];
+      rgb[3 * (size_t)id.p + 2] = palette[3 * lab + 2];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cross-lane reduction of 8 per-lane values to wave totals.
+// Three transpose stages halve the value set while exchanging with lane^1,
+// lane^2, lane^4 (DPP); lane^8 is a row rotation by 8; lane^16 and lane^32
+// use the gfx950 permlane swaps. Afterwards every lane holds the total of
+// value index bitrev3(lane & 7).
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+constexpr int kQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int kRowShl4 = 0x104;
+constexpr int kRowShr4 = 0x114;
+constexpr int kRowRor8 = 0x128;
+
+__device__ __forceinline__ float wave_total8(const float (&v)[8], int lane) {
+  const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+  float u[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float r0 = v[j] + dpp_mov<kQuadXor1>(v[j]);
+    float r1 = v[j + 4] + dpp_mov<kQuadXor1>(v[j + 4]);
+    u[j] = b0 ? r1 : r0;
+  }
+  float w[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    float r0 = u[j] + dpp_mov<kQuadXor2>(u[j]);
+    float r1 = u[j + 2] + dpp_mov<kQuadXor2>(u[j + 2]);
+    w[j] = b1 ? r1 : r0;
+  }
+  float r0 = w[0] + dpp_mov<kRowShl4>(w[0]);
+  float r1 = w[1] + dpp_mov<kRowShr4>(w[1]);
+  float t = b2 ? r1 : r0;
+  t += dpp_mov<kRowRor8>(t);
+  auto p16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(t), __float_as_uint(t), false, false);
+  t = __uint_as_float(p16[0]) + __uint_as_float(p16[1]);
+  auto p32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(t), __float_as_uint(t), false, false);
+  t = __uint_as_float(p32[0]) + __uint_as_float(p32[1]);
+  return t;
+}
+
+__device__ __forceinline__ int value_index_of_lane(int lane) {
+  return ((lane & 1) << 2) | (lane & 2) | ((lane >> 2) & 1);
+}
+
+// ---------------------------------------------------------------------------
+// Replay adjoint (Sec. 5.2): i = 1..N regenerates x_i = Phi_i(x_{i-1})
+// (Eq. rpos) and T_i (Eq. rT, multiplicative form), except where the side
+// table holds x_i (the floor bound there in the forward pass) or a
+// checkpoint resets the drift; then applies Eq. adjstep and accumulates
+// Eq. adjparam. Per stroke, 8 contributions (m_x, m_y, phi, l, r, c_rgb)
+// are reduced across the wave and then across the block's 4 waves in a
+// fixed order into the tile's partial row.
+// ---------------------------------------------------------------------------
+constexpr int kChunk = 32;
+
+__global__ void __launch_bounds__(256)
+    k_replay(const StrokeRec* __restrict__ recs, int n, int width, int height,
+             const float* __restrict__ palette, const float* __restrict__ grad_rgb, KTape tape,
+             float* __restrict__ partial) {
+  __shared__ float lds[2][4][kChunk][8];
+  const float bgr = palette[0], bgg = palette[1], bgb = palette[2];
+  PixelId id = pixel_of_thread(width, height);
+  const int P = width * height;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tile = blockIdx.y * gridDim.x + blockIdx.x;
+  float* prow = partial + (size_t)tile * (n + 1) * 8;
+  const int k = tape.ckpt_interval;
+
+  // seed: lambda^C = dL/dR (constant along the chain), lambda^T_0 = lambda^C . c_0
+  float lcr = 0.f, lcg = 0.f, lcb = 0.f;
+  double x = 0.5, y = 0.5;
+  float tm = 1.f;
+  int te = 0, top = 0, top_idx = -1;
+  if (id.active) {
+    lcr = grad_rgb[3 * (size_t)id.p + 0];
+    lcg = grad_rgb[3 * (size_t)id.p + 1];
+    lcb = grad_rgb[3 * (size_t)id.p + 2];
+    double2 s0 = tape.ckpt_xy[id.p];
+    float2 t0 = tape.ckpt_t[id.p];
+    x = s0.x;
+    y = s0.y;
+    tm = t0.x;
+    te = (int)t0.y;
+    top = min(tape.nrec[id.p], tape.side_slots);
+    top_idx = top > 0 ? tape.side_idx[(size_t)(top - 1) * P + id.p] : -1;
+  }
+  float lt = fmaf(lcr, bgr, fmaf(lcg, bgg, lcb * bgb));
+  float lx = 0.f, ly = 0.f;
+  // background colour gradient: dL/dc_0 = lambda^C T_0
+  {
+    float t0 = trans_value(tm, te);
+    float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, lcr * t0, lcg * t0, lcb * t0};
+    float tot = wave_total8(v, lane);
+    if (lane < 8) lds[0][wave][0][value_index_of_lane(lane)] = tot;
+    __syncthreads();
+    if (threadIdx.x < 8) {
+      float s = lds[0][0][0][threadIdx.x] + lds[0][1][0][threadIdx.x] +
+                lds[0][2][0][threadIdx.x] + lds[0][3][0][threadIdx.x];
+      prow[(size_t)n * 8 + threadIdx.x] = s;
+    }
+    __syncthreads();
+  }
+
+  for (int c0 = 0; c0 < n; c0 += kChunk) {
+    const int buf = (c0 / kChunk) & 1;
+    const int cn = min(kChunk, n - c0);
+    for (int j = 0; j < cn; ++j) {
+      const int i = c0 + j;  // stroke index (0-based); its input state is x_{i+1}
+      const StrokeRec g = load_rec(recs, i);
+      const bool ck = k > 0 && ((i + 1) % k) == 0 && (i + 1) < n;
+      const bool pop = top_idx == i;
+      double ax = x, ay = y;
+      if (pop) {
+        double2 r = tape.side_xy[(size_t)(top - 1) * P + id.p];
+        ax = r.x;
+        ay = r.y;
+        --top;
+        top_idx = top > 0 ? tape.side_idx[(size_t)(top - 1) * P + id.p] : -1;
+      }
+      float2 ckt = make_float2(1.f, 0.f);
+      if (ck && id.active) {
+        double2 r = tape.ckpt_xy[(size_t)((i + 1) / k) * P + id.p];
+        ckt = tape.ckpt_t[(size_t)((i + 1) / k) * P + id.p];
+        ax = r.x;
+        ay = r.y;
+      }
+      const bool loaded = pop || ck;
+      // One chart and one displacement serve both directions: for a
+      // regenerated step the chart is at x_{i-1} and Phi_i gives x_i
+      // (Eq. rpos); for a loaded step the chart is at x_i and psi_i gives
+      // the (discarded) x_{i-1}, whose geometry the adjoint needs.
+      Chart ca = chart(ax, ay, g);
+      Move mv = displace(ca, g, loaded);
+      float sb = ca.S + mv.dS, hb = ca.H + mv.dH;  // folded coordinates of the new point
+
+      VjpIn vi;
+      vi.sgs = ca.sgs;
+      vi.sgh = ca.sgh;
+      vi.w = ca.w;
+      vi.floored = mv.floored;
+      if (loaded) {  // in = chart point x_i, out = psi_i(x_i)
+        vi.s = ca.s;
+        vi.h = ca.h;
+        vi.sig = ca.sig;
+        vi.th = ca.th;
+        vi.sn = ca.sn;
+        vi.cs = ca.cs;
+        vi.Sp = sb;
+        vi.Hp = hb;
+        vi.rho = mv.sig_o;
+        vi.th_o = mv.th_o;
+        vi.sn_o = mv.sn_o;
+        vi.cs_o = mv.cs_o;
+      } else {  // in = regenerated x_i = Phi_i(x_{i-1}), out = chart point x_{i-1}
+        vi.s = ca.sgs * sb;
+        vi.h = ca.sgh * hb;
+        vi.sig = mv.sig_o;
+        vi.th = mv.th_o;
+        vi.sn = mv.sn_o;
+        vi.cs = mv.cs_o;
+        vi.Sp = ca.S;
+        vi.Hp = ca.H;
+        vi.rho = ca.sig;
+        vi.th_o = ca.th;
+        vi.sn_o = ca.sn;
+        vi.cs_o = ca.cs;
+      }
+      // new current position x_i
+      if (loaded) {
+        x = ax;
+        y = ay;
+      } else {
+        advance(x, y, ca, mv, g);
+      }
+      // coverage and transmittance at x_i
+      Cover cv = cover(vi.sig, g);
+      vi.z = cv.z;
+      vi.alpha = cv.alpha;
+      vi.q = cv.q;
+      vi.clamped = cv.clamped;
+      if (ck) {
+        tm = ckt.x;
+        te = (int)ckt.y;
+      } else {
+        tm *= cv.inv_q;  // T_i = T_{i-1} / (1 - alpha_i)
+        renorm(tm, te);
+      }
+      float t = trans_value(tm, te);
+      float lc = fmaf(lcr, g.cr, fmaf(lcg, g.cg, lcb * g.cb));
+      float mu = t * (lc - lt);
+      float ta = t * cv.alpha;
+      lt = fmaf(cv.q, lt, cv.alpha * lc);
+      VjpOut vo = vjp_step(vi, g, lx, ly, mu);
+      lx = vo.gx;
+      ly = vo.gy;
+      float v[8] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
+      float tot = wave_total8(v, lane);
+      if (lane < 8) lds[buf][wave][j][value_index_of_lane(lane)] = tot;
+    }
+    __syncthreads();
+    {
+      const int j = threadIdx.x >> 3, vv = threadIdx.x & 7;
+      if (j < cn) {
+        float s = lds[buf][0][j][vv] + lds[buf][1][j][vv] + lds[buf][2][j][vv] + lds[buf][3][j][vv];
+        prow[(size_t)(c0 + j) * 8 + vv] = s;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic finalize: sum tile rows in tile order (two stages, FP64),
+// then the chain rule to the program parameters.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+    k_sum_tiles(const float* __restrict__ partial, int rows8, int n_tiles, int tiles_per_group,
+                double* __restrict__ out) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows8) return;
+  int g = blockIdx.y;
+  int t0 = g * tiles_per_group, t1 = min(n_tiles, t0 + tiles_per_group);
+  double acc = 0.0;
+  for (int t = t0; t < t1; ++t) acc += (double)partial[(size_t)t * rows8 + e];
+  out[(size_t)g * rows8 + e] = acc;
+}
+
+__global__ void __launch_bounds__(256)
+    k_finalize(const double* __restrict__ groups, int n_groups, KProgram p, KOpts o,
+               KGrad grad, float* __restrict__ gcol, float* __restrict__ pal_terms) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > p.n) return;
+  double s[8];
+  for (int v = 0; v < 8; ++v) s[v] = 0.0;
+  const int rows8 = (p.n + 1) * 8;
+  for (int g = 0; g < n_groups; ++g)
+    for (int v = 0; v < 8; ++v) s[v] += groups[(size_t)g * rows8 + (size_t)i * 8 + v];
+  // colour gradient rows (stroke colours, then the background at row n)
+  gcol[3 * i + 0] = (float)s[5];
+  gcol[3 * i + 1] = (float)s[6];
+  gcol[3 * i + 2] = (float)s[7];
+  if (i == p.n) return;
+  grad.cx[i] = (float)s[0];
+  grad.cy[i] = (float)s[1];
+  // a drop's map and coverage are invariant under rotation about its centre:
+  // the angle gradient is exactly zero there (the sum above is rounding noise)
+  grad.angle[i] = p.length[i] == 0.f ? 0.f : (float)s[2];
+  grad.length[i] = p.length[i] < 0.f ? -(float)s[3] : (float)s[3];  // d|L|/dL, +1 at 0
+  grad.half_width[i] = (float)s[4];
+  // colour weights s_ik = softmax(z_i / tau_c)_k (one-hot argmax when tau_c = 0)
+  const float* z = p.logits + (size_t)i * p.k;
+  float* gz = grad.logits + (size_t)i * p.k;
+  float* pt = pal_terms + (size_t)i * p.k * 3;  // s_ik dL/dc_i, summed over i later
+  int best = 0;
+  float zmax = z[0];
+  for (int j = 1; j < p.k; ++j)
+    if (z[j] > zmax) {
+      zmax = z[j];
+      best = j;
+    }
+  if (o.tau_c > 0.f) {
+    // logits: dL/dz_ik = s_ik (g . P_k - g . c_i) / tau_c
+    float inv_tc = 1.0f / o.tau_c, tot = 0.f;
+    for (int j = 0; j < p.k; ++j) tot += expf((z[j] - zmax) * inv_tc);
+    float inv_tot = 1.0f / tot;
+    double gc = 0.0;
+    for (int j = 0; j < p.k; ++j) {
+      double sj = (double)(expf((z[j] - zmax) * inv_tc) * inv_tot);
+      gc += sj * (s[5] * p.palette[3 * j] + s[6] * p.palette[3 * j + 1] + s[7] * p.palette[3 * j + 2]);
+    }
+    for (int j = 0; j < p.k; ++j) {
+      double sj = (double)(expf((z[j] - zmax) * inv_tc) * inv_tot);
+      double gp = s[5] * p.palette[3 * j] + s[6] * p.palette[3 * j + 1] + s[7] * p.palette[3 * j + 2];
+      gz[j] = (float)(sj * (gp - gc) * (double)inv_tc);
+      pt[3 * j + 0] = (float)(sj * s[5]);
+      pt[3 * j + 1] = (float)(sj * s[6]);
+      pt[3 * j + 2] = (float)(sj * s[7]);
+    }
+  } else {
+    for (int j = 0; j < p.k; ++j) {
+      gz[j] = 0.f;
+      float sj = j == best ? 1.f : 0.f;
+      pt[3 * j + 0] = sj * (float)s[5];
+      pt[3 * j + 1] = sj * (float)s[6];
+      pt[3 * j + 2] = sj * (float)s[7];
+    }
+  }
+}
+
+// Palette gradient dL/dP_k = sum_i s_ik dL/dc_i (+ background at k = 0):
+// one block per (k, channel), strided partial sums then a fixed tree.
+__global__ void __launch_bounds__(256)
+    k_palette_grad(const float* __restrict__ pal_terms, int n, int kpal,
+                   const float* __restrict__ gcol, float* __restrict__ gpal) {
+  __shared__ double red[256];
+  const int e = blockIdx.x;  // k * 3 + channel
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += (double)pal_terms[(size_t)i * kpal * 3 + e];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gpal[e] = (float)(red[0] + (e < 3 ? (double)gcol[3 * n + e] : 0.0));
+}
+
+// Fixed-order sum of the per-block loss partials; loss = SSE / (3P).
+__global__ void k_loss_final(const float* __restrict__ part, int n_part, float inv_count,
+                             float* __restrict__ loss) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < n_part; j += blockDim.x) acc += part[j];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = (float)(red[0] * (double)inv_count);
+}
+
+// Adam on the packed parameter vector [cx|cy|angle|length|half_width|logits|palette]
+// with one learning rate per group; clamps r into [r_lo, r_hi] and L into
+// [-l_max, l_max].
+__global__ void __launch_bounds__(256)
+    k_adam(float* __restrict__ prm, const float* __restrict__ grd, float* __restrict__ m,
+           float* __restrict__ v, int n, int kpal, KAdam a) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  int total = 5 * n + n * kpal + 3 * kpal;
+  if (e >= total) return;
+  float lr;
+  int grp = e < 5 * n ? e / n : (e < 5 * n + n * kpal ? 5 : 6);
+  switch (grp) {
+    case 0:
+    case 1: lr = a.lr_centre; break;
+    case 2: lr = a.lr_angle; break;
+    case 3: lr = a.lr_length; break;
+    case 4: lr = a.lr_width; break;
+    case 5: lr = a.lr_logits; break;
+    default: lr = a.lr_palette; break;
+  }
+  float g = grd[e];
+  float mm = fmaf(a.beta1, m[e], (1.f - a.beta1) * g);
+  float vv = fmaf(a.beta2, v[e], (1.f - a.beta2) * g * g);
+  m[e] = mm;
+  v[e] = vv;
+  float mh = mm / a.bc1, vh = vv / a.bc2;
+  float p = prm[e] - lr * mh / (sqrtf(vh) + a.eps);
+  if (grp == 4) p = fminf(fmaxf(p, a.r_lo), a.r_hi);
+  if (grp == 3) p = fminf(fmaxf(p, -a.l_max), a.l_max);
+  if (grp == 6) p = fminf(fmaxf(p, 0.f), 1.f);
+  prm[e] = p;
+}
+
+}  // namespace tbr

@@ -1,0 +1,65 @@
+// tbr_kernels.hpp -- kernel argument blocks and launch-facing declarations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tbr_device.hpp"
+
+namespace tbr {
+
+struct KProgram {
+  int n, k;
+  const float *cx, *cy, *angle, *length, *half_width, *logits, *palette;
+};
+
+struct KOpts {
+  float tau, tau_min, tau_c, eps;
+};
+
+// Replay tape (all device memory, pixel-minor so a wave's accesses coalesce).
+struct KTape {
+  double2* ckpt_xy;    // [n_ckpt][P]: position of states x_0, x_k, x_2k, ... (FP64)
+  float2* ckpt_t;      // [n_ckpt][P]: their transmittance (Tm, Te), T = Tm 2^Te
+  int32_t* nrec;       // [P] records pushed per pixel
+  int32_t* side_idx;   // [side_slots][P] stroke index of each record
+  double2* side_xy;    // [side_slots][P] position x_i at the record (FP64)
+  int32_t* status;     // [1] max records over pixels (atomicMax)
+  int ckpt_interval;   // k (0: only the final state)
+  int side_slots;      // per-pixel capacity
+};
+
+// Optional L2 seed computed at the end of the soft trace (fit step).
+struct KSeed {
+  const float* target;  // [P*3] or null
+  float* grad_rgb;      // [P*3] dL/dR
+  float* loss_part;     // [n_blocks] sum of squared errors per block
+};
+
+struct KGrad {
+  float *cx, *cy, *angle, *length, *half_width, *logits, *palette;
+};
+
+struct KAdam {
+  float lr_centre, lr_angle, lr_length, lr_width, lr_logits, lr_palette;
+  float beta1, beta2, eps, bc1, bc2;
+  float r_lo, r_hi, l_max;
+};
+
+__global__ void k_stroke_prep(KProgram p, KOpts o, StrokeRec* out, int32_t* status);
+__global__ void k_trace_soft(const StrokeRec* recs, int n, int width, int height,
+                             const float* palette, float* rgb, KTape tape, KSeed seed);
+__global__ void k_trace_hard(const StrokeRec* recs, int n, int width, int height,
+                             const float* palette, float* rgb, int32_t* label, int32_t* owner);
+__global__ void k_replay(const StrokeRec* recs, int n, int width, int height, const float* palette,
+                         const float* grad_rgb, KTape tape, float* partial);
+__global__ void k_sum_tiles(const float* partial, int rows8, int n_tiles, int tiles_per_group,
+                            double* out);
+__global__ void k_finalize(const double* groups, int n_groups, KProgram p, KOpts o, KGrad grad,
+                           float* gcol, float* pal_terms);
+__global__ void k_palette_grad(const float* pal_terms, int n, int kpal, const float* gcol,
+                               float* gpal);
+__global__ void k_loss_final(const float* part, int n_part, float inv_count, float* loss);
+__global__ void k_adam(float* prm, const float* grd, float* m, float* v, int n, int kpal, KAdam a);
+
+}  // namespace tbr
