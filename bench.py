@@ -29,9 +29,12 @@ PEAK_FP32_FLOPS = 157.3e12
 # Algorithmic FP operations per pixel-stroke, counted from the formulas of
 # each phase (FMA = 2, every other FP32/FP64 operation incl. compare, select,
 # min/max, conversion and transcendental = 1); per-phase table in the design
-# notes. The path is ALU-bound: HBM traffic is ~0.3 B per pixel-stroke.
-FLOPS_FWD = 183      # soft forward step with tape: chart, coverage, composite, psi displacement
-FLOPS_REPLAY = 332   # replay step: chart, Phi displacement, coverage, T, VJP, wave reduction
+# notes. These are the counts of a stroke far from the pixel (coverage below
+# 7e-13, no coverage or colour terms), the case of >99% of pixel-strokes here;
+# a near stroke needs 20 (forward) / 41 (replay) more. The path is ALU-bound:
+# HBM traffic is ~0.3 B per pixel-stroke.
+FLOPS_FWD = 163      # soft forward step with tape: chart, psi displacement, advance
+FLOPS_REPLAY = 291   # replay step: chart, Phi displacement, advance, VJP, wave reduction
 # HBM bytes per k_replay launch at the bench workload, from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
 # in the same runs; valid only for the kernel sources it was measured on.
@@ -76,6 +79,28 @@ def cpu_baseline(w, prog, target_rgb, budget_s=12.0):
                       f"{w.width}x{w.height} x {w.n_strokes}-stroke workload ({dt:.1f} s)"}
 
 
+def ckpt_baseline(w, dprog, target, every=50, steps=2):
+    """PyTorch autograd with checkpoints every 50 strokes, same inputs: time
+    per fit step and peak HBM, beside the replay adjoint."""
+    import torch
+    from paper_2609_08722_amd.baseline_ckpt import CkptFit
+    fit = CkptFit({k: v.clone() for k, v in dprog.items()}, w.width, w.height, tau=w.tau,
+                  tau_c=w.tau_c, every=every)
+    fit.step(target)  # warm-up
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        loss = fit.step(target)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    peak = torch.cuda.max_memory_allocated()
+    del fit
+    torch.cuda.empty_cache()
+    return {"ms_per_step": dt * 1e3, "peak_hbm_bytes": int(peak), "checkpoint_every": every,
+            "loss": float(loss), "impl": "PyTorch ops + torch.utils.checkpoint, FP32"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +108,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="fit1024x1024_n2000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ckpt-baseline", action="store_true",
+                    help="skip the checkpointed-autograd PyTorch baseline")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this size (profiler calibration)")
     args = ap.parse_args()
@@ -216,6 +243,8 @@ def main():
         "paper_context": "fit step 0.52-0.55 s at 1024^2 x 2000 on one RTX PRO 4000 (FP32, fused "
                          "Triton): 3.8e9-4.0e9 pixel-stroke/s; different hardware, context only",
     }
+    if not args.no_ckpt_baseline:
+        out["ckpt_autograd_baseline"] = ckpt_baseline(w, dprog, target)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, prog, target_np)
     print(json.dumps(out), flush=True)

@@ -80,6 +80,11 @@ __global__ void __launch_bounds__(256)
   out[i] = g;
 }
 
+// Coverage below sigmoid(-28) = 7e-13 is skipped for a whole wave: 1 - alpha
+// then rounds to exactly 1.0f, so transmittance is unchanged bitwise and every
+// dropped colour / gradient term is below 2^-40 of the terms kept.
+constexpr float kFarZ = -28.f;
+
 // Wave-uniform load of a stroke record (the index is uniform, so the
 // compiler issues scalar loads).
 __device__ __forceinline__ StrokeRec load_rec(const StrokeRec* __restrict__ recs, int i) {
@@ -121,23 +126,33 @@ __global__ void __launch_bounds__(256)
   int nrec = 0;
   const bool write_tape = tape.ckpt_xy != nullptr && id.active;
   const int k = tape.ckpt_interval;
+  // states x_k, x_2k, ... (< x_n) are checkpointed; x_{i+1} is the input of
+  // stroke i, so the first one met going down is at i = floor((n-1)/k) k - 1
+  int next_ck = k > 0 ? ((n - 1) / k) * k - 1 : -1;
   for (int i = n - 1; i >= 0; --i) {
     const StrokeRec g = load_rec(recs, i);
-    // checkpoint of state x_{i+1} (input of stroke i), every k states
-    if (write_tape && k > 0 && ((i + 1) % k) == 0 && (i + 1) < n) {
-      size_t o = (size_t)((i + 1) / k) * P + id.p;
-      tape.ckpt_xy[o] = make_double2(x, y);
-      tape.ckpt_t[o] = make_float2(tm, (float)te);
+    if (i == next_ck) {
+      if (write_tape) {
+        size_t o = (size_t)((i + 1) / k) * P + id.p;
+        tape.ckpt_xy[o] = make_double2(x, y);
+        tape.ckpt_t[o] = make_float2(tm, (float)te);
+      }
+      next_ck -= k;
     }
     Chart c = chart(x, y, g);
-    Cover v = cover(c.sig, g);
-    float t = trans_value(tm, te);
-    float ta = t * v.alpha;
-    cr = fmaf(ta, g.cr, cr);
-    cg = fmaf(ta, g.cg, cg);
-    cb = fmaf(ta, g.cb, cb);
-    tm *= v.q;
-    renorm(tm, te);
+    // Coverage and compositing, unless the stroke is far from every pixel
+    // of the wave: then alpha < 7e-13, 1 - alpha rounds to 1 and T and C
+    // are unchanged to FP32 rounding.
+    if (!__all(((g.r - c.sig) * g.inv_wd < kFarZ) || !id.active)) {
+      Cover v = cover(c.sig, g);
+      float t = trans_value(tm, te);
+      float ta = t * v.alpha;
+      cr = fmaf(ta, g.cr, cr);
+      cg = fmaf(ta, g.cg, cg);
+      cb = fmaf(ta, g.cb, cb);
+      tm *= v.q;
+      renorm(tm, te);
+    }
     // backward map with the implemented floor; record where it binds
     Move mv = displace(c, g, true);
     if (mv.floored) {
@@ -277,6 +292,38 @@ __device__ __forceinline__ float wave_total8(const float (&v)[8], int lane) {
   return t;
 }
 
+// Same result when values 5..7 are zero (strokes far from the wave).
+__device__ __forceinline__ float wave_total5(const float (&v)[5], int lane) {
+  const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+  float u[4];
+  {
+    float r0 = v[0] + dpp_mov<kQuadXor1>(v[0]);
+    float r1 = v[4] + dpp_mov<kQuadXor1>(v[4]);
+    u[0] = b0 ? r1 : r0;
+  }
+#pragma unroll
+  for (int j = 1; j < 4; ++j) {
+    float r0 = v[j] + dpp_mov<kQuadXor1>(v[j]);
+    u[j] = b0 ? 0.f : r0;
+  }
+  float w[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    float r0 = u[j] + dpp_mov<kQuadXor2>(u[j]);
+    float r1 = u[j + 2] + dpp_mov<kQuadXor2>(u[j + 2]);
+    w[j] = b1 ? r1 : r0;
+  }
+  float r0 = w[0] + dpp_mov<kRowShl4>(w[0]);
+  float r1 = w[1] + dpp_mov<kRowShr4>(w[1]);
+  float t = b2 ? r1 : r0;
+  t += dpp_mov<kRowRor8>(t);
+  auto p16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(t), __float_as_uint(t), false, false);
+  t = __uint_as_float(p16[0]) + __uint_as_float(p16[1]);
+  auto p32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(t), __float_as_uint(t), false, false);
+  t = __uint_as_float(p32[0]) + __uint_as_float(p32[1]);
+  return t;
+}
+
 __device__ __forceinline__ int value_index_of_lane(int lane) {
   return ((lane & 1) << 2) | (lane & 2) | ((lane >> 2) & 1);
 }
@@ -340,57 +387,28 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
   }
 
+  // checkpointed states x_k, x_2k, ... (< x_n); x_{i+1} is the input of stroke i
+  int next_ck = (k > 0 && k < n) ? k - 1 : 0x7fffffff;
   for (int c0 = 0; c0 < n; c0 += kChunk) {
     const int buf = (c0 / kChunk) & 1;
     const int cn = min(kChunk, n - c0);
     for (int j = 0; j < cn; ++j) {
       const int i = c0 + j;  // stroke index (0-based); its input state is x_{i+1}
       const StrokeRec g = load_rec(recs, i);
-      const bool ck = k > 0 && ((i + 1) % k) == 0 && (i + 1) < n;
+      const bool ck = i == next_ck;
+      if (ck) next_ck = next_ck + k + 1 < n ? next_ck + k : 0x7fffffff;
       const bool pop = top_idx == i;
-      double ax = x, ay = y;
-      if (pop) {
-        double2 r = tape.side_xy[(size_t)(top - 1) * P + id.p];
-        ax = r.x;
-        ay = r.y;
-        --top;
-        top_idx = top > 0 ? tape.side_idx[(size_t)(top - 1) * P + id.p] : -1;
-      }
-      float2 ckt = make_float2(1.f, 0.f);
-      if (ck && id.active) {
-        double2 r = tape.ckpt_xy[(size_t)((i + 1) / k) * P + id.p];
-        ckt = tape.ckpt_t[(size_t)((i + 1) / k) * P + id.p];
-        ax = r.x;
-        ay = r.y;
-      }
-      const bool loaded = pop || ck;
-      // One chart and one displacement serve both directions: for a
-      // regenerated step the chart is at x_{i-1} and Phi_i gives x_i
-      // (Eq. rpos); for a loaded step the chart is at x_i and psi_i gives
-      // the (discarded) x_{i-1}, whose geometry the adjoint needs.
-      Chart ca = chart(ax, ay, g);
-      Move mv = displace(ca, g, loaded);
-      float sb = ca.S + mv.dS, hb = ca.H + mv.dH;  // folded coordinates of the new point
-
-      VjpIn vi;
-      vi.sgs = ca.sgs;
-      vi.sgh = ca.sgh;
-      vi.w = ca.w;
-      vi.floored = mv.floored;
-      if (loaded) {  // in = chart point x_i, out = psi_i(x_i)
-        vi.s = ca.s;
-        vi.h = ca.h;
-        vi.sig = ca.sig;
-        vi.th = ca.th;
-        vi.sn = ca.sn;
-        vi.cs = ca.cs;
-        vi.Sp = sb;
-        vi.Hp = hb;
-        vi.rho = mv.sig_o;
-        vi.th_o = mv.th_o;
-        vi.sn_o = mv.sn_o;
-        vi.cs_o = mv.cs_o;
-      } else {  // in = regenerated x_i = Phi_i(x_{i-1}), out = chart point x_{i-1}
+      float tot;
+      if (!ck && !__any(pop)) {
+        // Common case: every lane regenerates x_i = Phi_i(x_{i-1}) (Eq. rpos).
+        Chart ca = chart(x, y, g);
+        Move mv = displace(ca, g, false);
+        float sb = ca.S + mv.dS, hb = ca.H + mv.dH;
+        VjpIn vi;
+        vi.sgs = ca.sgs;
+        vi.sgh = ca.sgh;
+        vi.w = ca.w;
+        vi.floored = false;
         vi.s = ca.sgs * sb;
         vi.h = ca.sgh * hb;
         vi.sig = mv.sig_o;
@@ -403,37 +421,121 @@ __global__ void __launch_bounds__(256)
         vi.th_o = ca.th;
         vi.sn_o = ca.sn;
         vi.cs_o = ca.cs;
-      }
-      // new current position x_i
-      if (loaded) {
-        x = ax;
-        y = ay;
-      } else {
         advance(x, y, ca, mv, g);
-      }
-      // coverage and transmittance at x_i
-      Cover cv = cover(vi.sig, g);
-      vi.z = cv.z;
-      vi.alpha = cv.alpha;
-      vi.q = cv.q;
-      vi.clamped = cv.clamped;
-      if (ck) {
-        tm = ckt.x;
-        te = (int)ckt.y;
+        if (__all(((g.r - vi.sig) * g.inv_wd < kFarZ) || !id.active)) {
+          // far stroke: alpha, mu dalpha and the colour terms vanish to FP32
+          vi.z = 0.f;
+          vi.alpha = 0.f;
+          vi.q = 1.f;
+          vi.clamped = true;
+          VjpOut vo = vjp_step(vi, g, lx, ly, 0.f);
+          lx = vo.gx;
+          ly = vo.gy;
+          float v[5] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr};
+          tot = wave_total5(v, lane);
+        } else {
+          Cover cv = cover(vi.sig, g);
+          vi.z = cv.z;
+          vi.alpha = cv.alpha;
+          vi.q = cv.q;
+          vi.clamped = cv.clamped;
+          tm *= cv.inv_q;  // T_i = T_{i-1} / (1 - alpha_i)  (Eq. rT)
+          renorm(tm, te);
+          float t = trans_value(tm, te);
+          float lc = fmaf(lcr, g.cr, fmaf(lcg, g.cg, lcb * g.cb));
+          float mu = t * (lc - lt);
+          float ta = t * cv.alpha;
+          lt = fmaf(cv.q, lt, cv.alpha * lc);
+          VjpOut vo = vjp_step(vi, g, lx, ly, mu);
+          lx = vo.gx;
+          ly = vo.gy;
+          float v[8] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
+          tot = wave_total8(v, lane);
+        }
       } else {
-        tm *= cv.inv_q;  // T_i = T_{i-1} / (1 - alpha_i)
-        renorm(tm, te);
+        // Some lane takes x_i from the side table (the floor bound there in
+        // the forward pass) or the step is a checkpoint (drift reset).
+        double ax = x, ay = y;
+        if (pop) {
+          double2 r = tape.side_xy[(size_t)(top - 1) * P + id.p];
+          ax = r.x;
+          ay = r.y;
+          --top;
+          top_idx = top > 0 ? tape.side_idx[(size_t)(top - 1) * P + id.p] : -1;
+        }
+        float2 ckt = make_float2(1.f, 0.f);
+        if (ck && id.active) {
+          double2 r = tape.ckpt_xy[(size_t)((i + 1) / k) * P + id.p];
+          ckt = tape.ckpt_t[(size_t)((i + 1) / k) * P + id.p];
+          ax = r.x;
+          ay = r.y;
+        }
+        const bool loaded = pop || ck;
+        // One chart and one displacement serve both directions: for a
+        // regenerated lane the chart is at x_{i-1} and Phi_i gives x_i;
+        // for a loaded lane the chart is at x_i and psi_i gives the
+        // (discarded) x_{i-1}, whose geometry the adjoint needs.
+        Chart ca = chart(ax, ay, g);
+        Move mv = displace(ca, g, loaded);
+        float sb = ca.S + mv.dS, hb = ca.H + mv.dH;  // folded coordinates of the new point
+        VjpIn vi;
+        vi.sgs = ca.sgs;
+        vi.sgh = ca.sgh;
+        vi.w = ca.w;
+        vi.floored = mv.floored;
+        if (loaded) {  // in = chart point x_i, out = psi_i(x_i)
+          vi.s = ca.s;
+          vi.h = ca.h;
+          vi.sig = ca.sig;
+          vi.th = ca.th;
+          vi.sn = ca.sn;
+          vi.cs = ca.cs;
+          vi.Sp = sb;
+          vi.Hp = hb;
+          vi.rho = mv.sig_o;
+          vi.th_o = mv.th_o;
+          vi.sn_o = mv.sn_o;
+          vi.cs_o = mv.cs_o;
+          x = ax;
+          y = ay;
+        } else {  // in = regenerated x_i, out = chart point x_{i-1}
+          vi.s = ca.sgs * sb;
+          vi.h = ca.sgh * hb;
+          vi.sig = mv.sig_o;
+          vi.th = mv.th_o;
+          vi.sn = mv.sn_o;
+          vi.cs = mv.cs_o;
+          vi.Sp = ca.S;
+          vi.Hp = ca.H;
+          vi.rho = ca.sig;
+          vi.th_o = ca.th;
+          vi.sn_o = ca.sn;
+          vi.cs_o = ca.cs;
+          advance(x, y, ca, mv, g);
+        }
+        Cover cv = cover(vi.sig, g);
+        vi.z = cv.z;
+        vi.alpha = cv.alpha;
+        vi.q = cv.q;
+        vi.clamped = cv.clamped;
+        if (ck) {
+          tm = ckt.x;
+          te = (int)ckt.y;
+        } else {
+          tm *= cv.inv_q;
+          renorm(tm, te);
+        }
+        float t = trans_value(tm, te);
+        float lc = fmaf(lcr, g.cr, fmaf(lcg, g.cg, lcb * g.cb));
+        float mu = t * (lc - lt);
+        float ta = t * cv.alpha;
+        lt = fmaf(cv.q, lt, cv.alpha * lc);
+        VjpOut vo = vjp_step(vi, g, lx, ly, mu);
+        lx = vo.gx;
+        ly = vo.gy;
+        float v[8] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
+        tot = wave_total8(v, lane);
       }
-      float t = trans_value(tm, te);
-      float lc = fmaf(lcr, g.cr, fmaf(lcg, g.cg, lcb * g.cb));
-      float mu = t * (lc - lt);
-      float ta = t * cv.alpha;
-      lt = fmaf(cv.q, lt, cv.alpha * lc);
-      VjpOut vo = vjp_step(vi, g, lx, ly, mu);
-      lx = vo.gx;
-      ly = vo.gy;
-      float v[8] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
-      float tot = wave_total8(v, lane);
       if (lane < 8) lds[buf][wave][j][value_index_of_lane(lane)] = tot;
     }
     __syncthreads();
