@@ -6,6 +6,10 @@ trace with the replay tape, L2 seed, replay adjoint, deterministic gradient
 reduction, colour/palette chain rule and the Adam update (tbr_fit_step).
 The metric is pixel-stroke evaluations per second, P * N / step time.
 
+Also reported: the hard render of the fitted program, the checkpointed-
+autograd PyTorch baseline on the same inputs, a Poisson serving replay
+(continuous batching vs one request at a time) and the FP64 CPU oracle.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 Prints ONE JSON line. Only one GPU is used; --gpus above 1 exits.
 """
@@ -110,6 +114,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ckpt-baseline", action="store_true",
                     help="skip the checkpointed-autograd PyTorch baseline")
+    ap.add_argument("--serve-seconds", type=float, default=8.0,
+                    help="length of the Poisson serving replay (0 = skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this size (profiler calibration)")
     args = ap.parse_args()
@@ -245,6 +251,12 @@ def main():
     }
     if not args.no_ckpt_baseline:
         out["ckpt_autograd_baseline"] = ckpt_baseline(w, dprog, target)
+    if args.serve_seconds > 0:
+        from paper_2609_08722_amd.serve_driver import serving_benchmark
+        del fit
+        torch.cuda.empty_cache()
+        out["serving"] = serving_benchmark(duration=args.serve_seconds, warmup=1.0)
+        log(f"[bench] serving: {out['serving']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, prog, target_np)
     print(json.dumps(out), flush=True)

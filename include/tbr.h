@@ -167,6 +167,100 @@ tbr_status tbr_fit_step(int32_t n_strokes, int32_t n_palette, float* params, flo
                         const tbr_render_opts* opts, const float* target_rgb, float* loss,
                         void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of replay requests (the forward render above,
+ * for many programs, resolutions and modes arriving over time).
+ *
+ * A server owns a scheduler thread and a set of HIP streams (default
+ * priority). Programs are registered once and copied into the caller's
+ * device arena, where they stay resident. Each scheduler tick:
+ *   1. retires launches that finished, freeing their requests' slots and
+ *      arena bytes;
+ *   2. admits queued requests in FIFO order while a slot is free and the
+ *      arena can hold the request's prepared stroke records (its footprint,
+ *      tbr_serve_request_bytes);
+ *   3. packs all admitted requests into one persistent launch over
+ *      (request, 16x16 tile) work items.
+ * Launches rotate over `streams` streams, so requests admitted while others
+ * run overlap with them on the device. Every pixel is computed by the same
+ * device code as tbr_render, so a request's result does not depend on what
+ * else is in flight. Output buffers belong to the caller and must stay valid
+ * until the ticket completes.
+ * ------------------------------------------------------------------------- */
+typedef struct tbr_server tbr_server;
+
+typedef struct tbr_serve_opts {
+  void* arena;                    /* device memory owned by the caller (NULL only with fake_device) */
+  size_t arena_bytes;             /* programs + admitted requests + per-stream launch buffers */
+  int32_t max_slots;              /* requests admitted (in flight) at once, >= 1 */
+  int32_t max_queue;              /* requests waiting for admission, >= 1 */
+  int32_t max_tick_items;         /* (request, tile) work items per launch, >= 1 */
+  int32_t streams;                /* launches in flight at once, 1..4 */
+  int32_t fake_device;            /* 1: host-only executor for scheduler tests; no GPU work */
+  float fake_ns_per_pixel_stroke; /* fake executor: modelled cost per pixel-stroke */
+} tbr_serve_opts;
+
+typedef struct tbr_request {
+  uint64_t program_id;            /* from tbr_serve_register_program */
+  int32_t mode;                   /* TBR_SOFT or TBR_HARD */
+  int32_t width, height;          /* 1 .. 16384 */
+  float tau, tau_min, tau_c, eps_floor;  /* as tbr_render_opts; tau_min <= 0 means
+                                            (float)(0.7 / (double)width) */
+  float* rgb;                     /* device [H*W*3]: soft composite, or hard colour (may be NULL for hard) */
+  int32_t* label;                 /* hard: device [H*W] or NULL */
+  int32_t* owner;                 /* hard: device [H*W] or NULL */
+} tbr_request;
+
+typedef struct tbr_result {
+  int32_t status;                 /* TBR_OK, TBR_PENDING, TBR_E_CANCELLED or TBR_E_DEVICE */
+  double t_submit, t_admit, t_start, t_done;  /* seconds on tbr_serve_now()'s clock */
+  int64_t pixel_strokes;          /* width * height * n_strokes */
+} tbr_result;
+
+typedef struct tbr_serve_stats {
+  int64_t submitted, completed, cancelled, launches;
+  int64_t pixel_strokes;          /* of completed requests */
+  int64_t queued, in_flight;
+  size_t arena_used, arena_bytes;
+} tbr_serve_stats;
+
+/* Arena bytes of one resident program, of one admitted request, and of the
+ * per-stream launch buffers (the arena must hold streams * tick bytes plus
+ * the programs plus the in-flight requests). */
+size_t tbr_serve_program_bytes(int32_t n_strokes, int32_t n_palette);
+size_t tbr_serve_request_bytes(int32_t n_strokes);
+size_t tbr_serve_tick_bytes(const tbr_serve_opts* opts);
+
+/* Create a server (starts its scheduler thread). */
+tbr_status tbr_serve_create(const tbr_serve_opts* opts, tbr_server** server);
+
+/* Copy a program (device arrays) into the arena; synchronous. TBR_E_NOMEM
+ * when the arena cannot hold it. */
+tbr_status tbr_serve_register_program(tbr_server* server, const tbr_program* program,
+                                      uint64_t* program_id);
+
+/* Queue a request; returns at once with a ticket. TBR_E_CAPACITY when the
+ * queue is full, TBR_E_NOMEM when the request could never be admitted,
+ * TBR_E_NOTFOUND for an unknown program. */
+tbr_status tbr_serve_submit(tbr_server* server, const tbr_request* request, uint64_t* ticket);
+
+/* TBR_OK (request finished; its outputs are complete on the device) or
+ * TBR_E_CANCELLED, after which the ticket is forgotten; TBR_PENDING while
+ * queued or running. Fills *result in every case. Does not synchronise. */
+tbr_status tbr_serve_poll(tbr_server* server, uint64_t ticket, tbr_result* result);
+
+/* Cancel a queued request (TBR_OK); an admitted one runs to completion
+ * (TBR_PENDING). */
+tbr_status tbr_serve_cancel(tbr_server* server, uint64_t ticket);
+
+tbr_status tbr_serve_get_stats(tbr_server* server, tbr_serve_stats* stats);
+
+/* Stop the scheduler, wait for launches in flight, free host resources. */
+void tbr_serve_destroy(tbr_server* server);
+
+/* The serving clock (steady, seconds). */
+double tbr_serve_now(void);
+
 /* Optional timing hook for benchmarks. While set on the calling thread,
  * every launch of the kernel named `kernel` ("trace_soft", "trace_hard" or
  * "replay") made by a tbr_* call on this thread is bracketed by

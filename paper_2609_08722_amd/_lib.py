@@ -51,6 +51,31 @@ class AdamOpts(C.Structure):
                 ("step", C.c_int32)]
 
 
+class ServeOpts(C.Structure):
+    _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("max_slots", C.c_int32),
+                ("max_queue", C.c_int32), ("max_tick_items", C.c_int32), ("streams", C.c_int32),
+                ("fake_device", C.c_int32), ("fake_ns_per_pixel_stroke", C.c_float)]
+
+
+class Request(C.Structure):
+    _fields_ = [("program_id", C.c_uint64), ("mode", C.c_int32), ("width", C.c_int32),
+                ("height", C.c_int32), ("tau", C.c_float), ("tau_min", C.c_float),
+                ("tau_c", C.c_float), ("eps_floor", C.c_float), ("rgb", C.c_void_p),
+                ("label", C.c_void_p), ("owner", C.c_void_p)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double), ("pixel_strokes", C.c_int64)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("cancelled", C.c_int64),
+                ("launches", C.c_int64), ("pixel_strokes", C.c_int64), ("queued", C.c_int64),
+                ("in_flight", C.c_int64), ("arena_used", C.c_size_t),
+                ("arena_bytes", C.c_size_t)]
+
+
 # Every exported symbol of include/tbr.h, with its ctypes signature.
 _vp, _sz, _i32 = C.c_void_p, C.c_size_t, C.c_int32
 SIGNATURES = {
@@ -62,6 +87,17 @@ SIGNATURES = {
     "tbr_fit_workspace_bytes": (_sz, [_vp, _i32, _i32]),
     "tbr_fit_step": (_i32, [_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "tbr_set_timing_events": (_i32, [C.c_char_p, _vp, _vp]),
+    "tbr_serve_program_bytes": (_sz, [_i32, _i32]),
+    "tbr_serve_request_bytes": (_sz, [_i32]),
+    "tbr_serve_tick_bytes": (_sz, [_vp]),
+    "tbr_serve_create": (_i32, [_vp, _vp]),
+    "tbr_serve_register_program": (_i32, [_vp, _vp, _vp]),
+    "tbr_serve_submit": (_i32, [_vp, _vp, _vp]),
+    "tbr_serve_poll": (_i32, [_vp, C.c_uint64, _vp]),
+    "tbr_serve_cancel": (_i32, [_vp, C.c_uint64]),
+    "tbr_serve_get_stats": (_i32, [_vp, _vp]),
+    "tbr_serve_destroy": (None, [_vp]),
+    "tbr_serve_now": (C.c_double, []),
     "tbr_last_error": (C.c_char_p, []),
     "tbr_version": (C.c_char_p, []),
 }

@@ -259,3 +259,84 @@ class FitState:
     def grow_side_table(self, slots: int):
         self.opts = Opts(**{**self.opts.__dict__, "side_slots": int(slots)})
         self._alloc()
+
+
+class Server:
+    """Continuous-batching server of replay requests (tbr_serve_*).
+
+    The device arena is a torch uint8 tensor owned by this object; programs
+    are copied into it once. submit() returns a ticket at once; poll() says
+    when the request's outputs are complete on the device."""
+
+    def __init__(self, arena_bytes: int = 256 << 20, max_slots: int = 64, max_queue: int = 4096,
+                 max_tick_items: int = 1 << 17, streams: int = 3, fake_device: bool = False,
+                 fake_ns_per_pixel_stroke: float = 0.0, device="cuda"):
+        lib = L.load()
+        self.arena = None if fake_device else torch.empty(arena_bytes, dtype=torch.uint8,
+                                                          device=device)
+        self.opts = L.ServeOpts(_ptr(self.arena), int(arena_bytes), int(max_slots),
+                                int(max_queue), int(max_tick_items), int(streams),
+                                int(fake_device), float(fake_ns_per_pixel_stroke))
+        h = C.c_void_p()
+        L.check(lib.tbr_serve_create(C.byref(self.opts), C.byref(h)))
+        self.h = h
+        self.fake = fake_device
+        self._keep = {}
+
+    def register(self, prog: dict) -> int:
+        lib = L.load()
+        if self.fake:
+            n = len(prog["cx"])
+            k = np.asarray(prog["palette"]).reshape(-1, 3).shape[0]
+            cp = L.Program(n, k, *([None] * 7))
+        else:
+            cp = c_program(prog)
+        pid = C.c_uint64()
+        L.check(lib.tbr_serve_register_program(self.h, C.byref(cp), C.byref(pid)))
+        return pid.value
+
+    def submit(self, program_id: int, mode: str, width: int, height: int, rgb=None, label=None,
+               owner=None, tau=1e-3, tau_min=0.0, tau_c=0.0, eps=1e-3) -> int:
+        lib = L.load()
+        r = L.Request(int(program_id), L.TBR_SOFT if mode == "soft" else L.TBR_HARD, int(width),
+                      int(height), float(tau), float(tau_min), float(tau_c), float(eps),
+                      _ptr(rgb), _ptr(label), _ptr(owner))
+        t = C.c_uint64()
+        L.check(lib.tbr_serve_submit(self.h, C.byref(r), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending; else a dict with status and timestamps."""
+        lib = L.load()
+        res = L.Result()
+        st = lib.tbr_serve_poll(self.h, C.c_uint64(ticket), C.byref(res))
+        if st == L.TBR_PENDING:
+            return None
+        if st not in (L.TBR_OK, L.TBR_E_CANCELLED):
+            L.check(st)
+        return {"status": st, "t_submit": res.t_submit, "t_admit": res.t_admit,
+                "t_start": res.t_start, "t_done": res.t_done,
+                "pixel_strokes": res.pixel_strokes}
+
+    def cancel(self, ticket: int) -> int:
+        return L.load().tbr_serve_cancel(self.h, C.c_uint64(ticket))
+
+    def stats(self) -> dict:
+        s = L.ServeStats()
+        L.check(L.load().tbr_serve_get_stats(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in L.ServeStats._fields_}
+
+    @staticmethod
+    def now() -> float:
+        return L.load().tbr_serve_now()
+
+    def close(self):
+        if self.h:
+            L.load().tbr_serve_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

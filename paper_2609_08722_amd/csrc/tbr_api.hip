@@ -14,9 +14,11 @@
 
 using namespace tbr;
 
-namespace {
+namespace tbr {
+thread_local std::string g_err;  // last error message of this thread (all entry points)
+}  // namespace tbr
 
-thread_local std::string g_err;
+namespace {
 
 tbr_status fail(tbr_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 tbr_status fail(tbr_status s, const char* fmt, ...) {

@@ -98,11 +98,11 @@ struct PixelId {
   int p;  // flat index (clamped inside the canvas for inactive lanes)
 };
 
-__device__ __forceinline__ PixelId pixel_of_thread(int width, int height) {
+__device__ __forceinline__ PixelId pixel_of_tile(int tx, int ty, int width, int height) {
   PixelId id;
   int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  id.px = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
-  id.py = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
+  id.px = tx * 16 + (wave & 1) * 8 + (lane & 7);
+  id.py = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
   id.active = id.px < width && id.py < height;
   int cx = min(id.px, width - 1), cy = min(id.py, height - 1);
   id.p = cy * width + cx;
@@ -110,13 +110,21 @@ __device__ __forceinline__ PixelId pixel_of_thread(int width, int height) {
 }
 
 // ---------------------------------------------------------------------------
-// Soft forward trace (Eq. chain + Eq. render with Eq. relax), optional tape.
+// Soft forward trace (Eq. chain + Eq. render with Eq. relax) of one pixel
+// per lane, optionally writing the replay tape. Shared by the render, the
+// fit step and the serving kernel, so a pixel's result does not depend on
+// which launch computed it.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
-    k_trace_soft(const StrokeRec* __restrict__ recs, int n, int width, int height,
-                 const float* __restrict__ palette, float* __restrict__ rgb, KTape tape, KSeed seed) {
-  PixelId id = pixel_of_thread(width, height);
-  const float bgr = palette[0], bgg = palette[1], bgb = palette[2];  // c_0 = P[0]
+struct SoftOut {
+  float cr, cg, cb;  // composite R = C_0 + T_0 c_0
+  int nrec;          // records pushed (floor bound)
+};
+
+template <bool kTape>
+__device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs, int n,
+                                              const PixelId& id, int width, int height,
+                                              const float* __restrict__ palette,
+                                              const KTape& tape) {
   const int P = width * height;
   double x = (id.px + 0.5) / (double)width;
   double y = (id.py + 0.5) / (double)height;
@@ -124,14 +132,14 @@ __global__ void __launch_bounds__(256)
   float tm = 1.0f;
   int te = 0;
   int nrec = 0;
-  const bool write_tape = tape.ckpt_xy != nullptr && id.active;
-  const int k = tape.ckpt_interval;
+  const bool write_tape = kTape && id.active;
+  const int k = kTape ? tape.ckpt_interval : 0;
   // states x_k, x_2k, ... (< x_n) are checkpointed; x_{i+1} is the input of
   // stroke i, so the first one met going down is at i = floor((n-1)/k) k - 1
   int next_ck = k > 0 ? ((n - 1) / k) * k - 1 : -1;
   for (int i = n - 1; i >= 0; --i) {
     const StrokeRec g = load_rec(recs, i);
-    if (i == next_ck) {
+    if (kTape && i == next_ck) {
       if (write_tape) {
         size_t o = (size_t)((i + 1) / k) * P + id.p;
         tape.ckpt_xy[o] = make_double2(x, y);
@@ -166,26 +174,64 @@ __global__ void __launch_bounds__(256)
     advance(x, y, c, mv, g);
   }
   float t = trans_value(tm, te);
-  cr = fmaf(t, bgr, cr);
-  cg = fmaf(t, bgg, cg);
-  cb = fmaf(t, bgb, cb);
-  if (id.active && rgb) {
-    rgb[3 * (size_t)id.p + 0] = cr;
-    rgb[3 * (size_t)id.p + 1] = cg;
-    rgb[3 * (size_t)id.p + 2] = cb;
-  }
+  SoftOut o;
+  o.cr = fmaf(t, palette[0], cr);  // background c_0 = P[0]
+  o.cg = fmaf(t, palette[1], cg);
+  o.cb = fmaf(t, palette[2], cb);
+  o.nrec = nrec;
   if (write_tape) {  // state x_0
     tape.ckpt_xy[id.p] = make_double2(x, y);
     tape.ckpt_t[id.p] = make_float2(tm, (float)te);
     tape.nrec[id.p] = nrec;
   }
+  return o;
+}
+
+// Hard trace of one pixel per lane: first footprint hit going N -> 1; lanes
+// retire on a hit and the wave leaves the stroke loop once all have retired.
+__device__ __forceinline__ void hard_pixel(const StrokeRec* __restrict__ recs, int n,
+                                           const PixelId& id, int width, int height, int& own,
+                                           int& lab) {
+  double x = (id.px + 0.5) / (double)width;
+  double y = (id.py + 0.5) / (double)height;
+  bool done = !id.active;
+  own = -1;
+  lab = 0;
+  for (int i = n - 1; i >= 0; --i) {
+    if (__all(done)) break;
+    const StrokeRec g = load_rec(recs, i);
+    if (!done) {
+      Chart c = chart(x, y, g);
+      if (c.sig <= g.r) {  // closed footprint
+        done = true;
+        own = i;
+        lab = g.label;
+      } else {
+        advance(x, y, c, displace(c, g, true), g);
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    k_trace_soft(const StrokeRec* __restrict__ recs, int n, int width, int height,
+                 const float* __restrict__ palette, float* __restrict__ rgb, KTape tape, KSeed seed) {
+  PixelId id = pixel_of_tile(blockIdx.x, blockIdx.y, width, height);
+  const int P = width * height;
+  SoftOut o = tape.ckpt_xy ? soft_pixel<true>(recs, n, id, width, height, palette, tape)
+                           : soft_pixel<false>(recs, n, id, width, height, palette, tape);
+  if (id.active && rgb) {
+    rgb[3 * (size_t)id.p + 0] = o.cr;
+    rgb[3 * (size_t)id.p + 1] = o.cg;
+    rgb[3 * (size_t)id.p + 2] = o.cb;
+  }
   // L2 seed (fit step): lambda^C_0 = dL/dR = 2 (R - I*) / (3P), loss partials
   if (seed.target) {
     float sq = 0.f;
     if (id.active) {
-      float dr = cr - seed.target[3 * (size_t)id.p + 0];
-      float dg = cg - seed.target[3 * (size_t)id.p + 1];
-      float db = cb - seed.target[3 * (size_t)id.p + 2];
+      float dr = o.cr - seed.target[3 * (size_t)id.p + 0];
+      float dg = o.cg - seed.target[3 * (size_t)id.p + 1];
+      float db = o.cb - seed.target[3 * (size_t)id.p + 2];
       float sc = 2.0f / (3.0f * (float)P);
       seed.grad_rgb[3 * (size_t)id.p + 0] = sc * dr;
       seed.grad_rgb[3 * (size_t)id.p + 1] = sc * dg;
@@ -204,39 +250,19 @@ __global__ void __launch_bounds__(256)
   }
   if (tape.status) {
     // max record count over the wave, one atomic per wave
-    int m = id.active ? nrec : 0;
+    int m = id.active ? o.nrec : 0;
     for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
-    if ((threadIdx.x & 63) == 0 && tape.status) atomicMax(tape.status, m);
+    if ((threadIdx.x & 63) == 0) atomicMax(tape.status, m);
   }
 }
 
-// ---------------------------------------------------------------------------
-// Hard trace: first footprint hit going N -> 1; lanes retire on a hit and
-// the wave leaves the stroke loop once every lane has retired (ballot).
-// ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
     k_trace_hard(const StrokeRec* __restrict__ recs, int n, int width, int height,
                  const float* __restrict__ palette, float* __restrict__ rgb,
                  int32_t* __restrict__ label, int32_t* __restrict__ owner) {
-  PixelId id = pixel_of_thread(width, height);
-  double x = (id.px + 0.5) / (double)width;
-  double y = (id.py + 0.5) / (double)height;
-  bool done = !id.active;
-  int own = -1, lab = 0;
-  for (int i = n - 1; i >= 0; --i) {
-    if (__all(done)) break;
-    const StrokeRec g = load_rec(recs, i);
-    if (!done) {
-      Chart c = chart(x, y, g);
-      if (c.sig <= g.r) {  // closed footprint
-        done = true;
-        own = i;
-        lab = g.label;
-      } else {
-        advance(x, y, c, displace(c, g, true), g);
-      }
-    }
-  }
+  PixelId id = pixel_of_tile(blockIdx.x, blockIdx.y, width, height);
+  int own, lab;
+  hard_pixel(recs, n, id, width, height, own, lab);
   if (id.active) {
     if (owner) owner[id.p] = own;
     if (label) label[id.p] = lab;
@@ -246,6 +272,56 @@ __global__ void __launch_bounds__(256)
       rgb[3 * (size_t)id.p + 2] = palette[3 * lab + 2];
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Serving: one persistent launch per scheduler tick. Blocks pull
+// (request, tile) work items through an atomic cursor until the list is
+// exhausted (every block exits when the cursor passes n_items), so tiles of
+// requests with different programs, resolutions and modes share the device.
+// Each tile runs the same per-pixel functions as the single-request kernels.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+    k_serve(const ServeDesc* __restrict__ descs, const uint2* __restrict__ items, int n_items,
+            int* __restrict__ cursor) {
+  __shared__ int item_s;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = atomicAdd(cursor, 1);
+    __syncthreads();
+    const int it = item_s;
+    __syncthreads();
+    if (it >= n_items) break;
+    const uint2 w = items[it];
+    const ServeDesc d = descs[__builtin_amdgcn_readfirstlane(w.x)];
+    const int tile = __builtin_amdgcn_readfirstlane(w.y);
+    PixelId id = pixel_of_tile(tile % d.tiles_x, tile / d.tiles_x, d.width, d.height);
+    if (d.soft) {
+      KTape none{};
+      SoftOut o = soft_pixel<false>(d.recs, d.n, id, d.width, d.height, d.palette, none);
+      if (id.active) {
+        d.rgb[3 * (size_t)id.p + 0] = o.cr;
+        d.rgb[3 * (size_t)id.p + 1] = o.cg;
+        d.rgb[3 * (size_t)id.p + 2] = o.cb;
+      }
+    } else {
+      int own, lab;
+      hard_pixel(d.recs, d.n, id, d.width, d.height, own, lab);
+      if (id.active) {
+        if (d.owner) d.owner[id.p] = own;
+        if (d.label) d.label[id.p] = lab;
+        if (d.rgb) {
+          d.rgb[3 * (size_t)id.p + 0] = d.palette[3 * lab + 0];
+          d.rgb[3 * (size_t)id.p + 1] = d.palette[3 * lab + 1];
+          d.rgb[3 * (size_t)id.p + 2] = d.palette[3 * lab + 2];
+        }
+      }
+    }
+  }
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int n, int v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -345,7 +421,7 @@ __global__ void __launch_bounds__(256)
              float* __restrict__ partial) {
   __shared__ float lds[2][4][kChunk][8];
   const float bgr = palette[0], bgg = palette[1], bgb = palette[2];
-  PixelId id = pixel_of_thread(width, height);
+  PixelId id = pixel_of_tile(blockIdx.x, blockIdx.y, width, height);
   const int P = width * height;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tile = blockIdx.y * gridDim.x + blockIdx.x;

@@ -40,6 +40,18 @@ struct KGrad {
   float *cx, *cy, *angle, *length, *half_width, *logits, *palette;
 };
 
+// One admitted serving request (device copy, read by k_serve).
+struct ServeDesc {
+  const StrokeRec* recs;  // prepared records of the request's program and options
+  const float* palette;   // [K*3]
+  float* rgb;             // [H*W*3] or null (hard)
+  int32_t* label;         // [H*W] or null
+  int32_t* owner;         // [H*W] or null
+  int n, width, height, tiles_x;
+  int soft;               // 1 soft composite, 0 hard
+  int pad[3];
+};
+
 struct KAdam {
   float lr_centre, lr_angle, lr_length, lr_width, lr_logits, lr_palette;
   float beta1, beta2, eps, bc1, bc2;
@@ -61,5 +73,7 @@ __global__ void k_palette_grad(const float* pal_terms, int n, int kpal, const fl
                                float* gpal);
 __global__ void k_loss_final(const float* part, int n_part, float inv_count, float* loss);
 __global__ void k_adam(float* prm, const float* grd, float* m, float* v, int n, int kpal, KAdam a);
+__global__ void k_serve(const ServeDesc* descs, const uint2* items, int n_items, int* cursor);
+__global__ void k_fill_i32(int32_t* p, int n, int v);
 
 }  // namespace tbr

@@ -1,0 +1,544 @@
+// tbr_serve.hip -- continuous batching of replay requests (tbr_serve_* in
+// include/tbr.h).
+//
+// A scheduler thread owns the device side. Registered programs are copied
+// once into a caller-provided device arena and stay resident. Submitted
+// requests wait in a FIFO; each scheduler tick
+//   1. retires finished launches (their HIP event has completed), freeing
+//      the requests' arena bytes and slots,
+//   2. admits queued requests in order while a slot is free and the arena
+//      can hold the request's prepared stroke records (its HBM footprint),
+//   3. packs every admitted-but-not-launched request into ONE persistent
+//      launch (k_serve) over a list of (request, 16x16 tile) work items,
+//      after launching the per-request stroke preparation on the same
+//      stream.
+// Launches rotate over several streams, so requests admitted while others
+// are still on the GPU run concurrently with them. Each tile runs the same
+// per-pixel device functions as tbr_render, so results do not depend on the
+// mix. A host-only "fake device" executor (no HIP calls) models completion
+// time for scheduler tests on machines without a GPU.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "tbr.h"
+#include "tbr_kernels.hpp"
+
+using namespace tbr;
+
+namespace tbr {
+extern thread_local std::string g_err;  // shared with tbr_last_error()
+}  // namespace tbr
+
+namespace {
+
+tbr_status sfail(tbr_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+tbr_status sfail(tbr_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit allocator over [0, size) with coalescing free list.
+class Arena {
+ public:
+  void init(size_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+    size_ = size;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = align_up(bytes ? bytes : 1);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        size_t rest = it->second - bytes, start = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[start] = rest;
+        used_ += bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = align_up(bytes ? bytes : 1);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+  size_t size() const { return size_; }
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t size_ = 0, used_ = 0;
+};
+
+struct Program {
+  int n, k;
+  size_t off = 0, bytes = 0;  // arena copy: cx|cy|angle|length|half_width|logits|palette
+};
+
+enum ReqState { kQueued, kAdmitted, kRunning, kDone, kCancelled };
+
+struct Request {
+  tbr_request req;
+  uint64_t ticket;
+  int n = 0, k = 0;
+  size_t rec_off = 0, rec_bytes = 0;
+  int tiles = 0;
+  ReqState state = kQueued;
+  double t_submit = 0, t_admit = 0, t_start = 0, t_done = 0;
+};
+
+struct Tick {
+  bool busy = false;
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  size_t desc_off = 0, item_off = 0, cursor_off = 0;
+  ServeDesc* h_desc = nullptr;  // pinned staging
+  uint2* h_items = nullptr;
+  std::vector<uint64_t> tickets;
+  double fake_done = 0;  // fake executor: modelled completion time
+};
+
+}  // namespace
+
+struct tbr_server {
+  tbr_serve_opts opts{};
+  char* base = nullptr;
+  Arena arena;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::thread worker;
+  bool stop = false;
+  uint64_t next_program = 1, next_ticket = 1;
+  std::map<uint64_t, Program> programs;
+  std::map<uint64_t, Request> requests;
+  std::deque<uint64_t> queue;    // submitted, not admitted (FIFO)
+  std::vector<uint64_t> ready;   // admitted, not launched
+  std::vector<Tick> ticks;
+  int admitted = 0;              // admitted or running
+  tbr_serve_stats stats{};
+  std::string error;             // first device error (fatal for the server)
+};
+
+namespace {
+
+size_t program_bytes(int n, int k) {
+  return align_up(((size_t)5 * n + (size_t)n * k + (size_t)3 * k) * sizeof(float));
+}
+size_t record_bytes(int n) { return align_up((size_t)(n > 0 ? n : 1) * sizeof(StrokeRec)); }
+
+int tiles_of(const tbr_request& r) {
+  return ((r.width + 15) / 16) * ((r.height + 15) / 16);
+}
+
+// Called with the lock held.
+void retire(tbr_server* s) {
+  const double t = now_s();
+  for (auto& tk : s->ticks) {
+    if (!tk.busy) continue;
+    bool finished;
+    if (s->opts.fake_device) {
+      finished = t >= tk.fake_done;
+    } else {
+      hipError_t e = hipEventQuery(tk.done);
+      if (e == hipErrorNotReady) continue;
+      if (e != hipSuccess && s->error.empty()) s->error = hipGetErrorString(e);
+      finished = true;
+    }
+    if (!finished) continue;
+    for (uint64_t id : tk.tickets) {
+      auto it = s->requests.find(id);
+      if (it == s->requests.end()) continue;
+      Request& r = it->second;
+      r.state = kDone;
+      r.t_done = t;
+      s->arena.release(r.rec_off, r.rec_bytes);
+      --s->admitted;
+      ++s->stats.completed;
+      s->stats.pixel_strokes += (int64_t)r.req.width * r.req.height * r.n;
+    }
+    tk.tickets.clear();
+    tk.busy = false;
+  }
+}
+
+void admit(tbr_server* s) {
+  const double t = now_s();
+  while (!s->queue.empty() && s->admitted < s->opts.max_slots) {
+    uint64_t id = s->queue.front();
+    Request& r = s->requests[id];
+    size_t off;
+    if (!s->arena.alloc(r.rec_bytes, &off)) break;  // wait for memory (FIFO)
+    r.rec_off = off;
+    r.state = kAdmitted;
+    r.t_admit = t;
+    s->queue.pop_front();
+    s->ready.push_back(id);
+    ++s->admitted;
+  }
+}
+
+tbr_status launch(tbr_server* s) {
+  if (s->ready.empty()) return TBR_OK;
+  Tick* tk = nullptr;
+  for (auto& c : s->ticks)
+    if (!c.busy) {
+      tk = &c;
+      break;
+    }
+  if (!tk) return TBR_OK;
+  // pack ready requests (in admission order) while the work list has room
+  std::vector<uint64_t> take;
+  int n_items = 0;
+  size_t used = 0;
+  for (uint64_t id : s->ready) {
+    Request& r = s->requests[id];
+    if (take.size() >= (size_t)s->opts.max_slots) break;
+    if (n_items + r.tiles > s->opts.max_tick_items) break;
+    take.push_back(id);
+    n_items += r.tiles;
+    ++used;
+  }
+  if (take.empty()) return TBR_OK;
+  s->ready.erase(s->ready.begin(), s->ready.begin() + used);
+  const double t = now_s();
+  tk->busy = true;
+  tk->tickets = take;
+  ++s->stats.launches;
+  if (s->opts.fake_device) {
+    double cost = 0;
+    for (uint64_t id : take) {
+      Request& r = s->requests[id];
+      r.state = kRunning;
+      r.t_start = t;
+      cost += (double)r.req.width * r.req.height * r.n * s->opts.fake_ns_per_pixel_stroke * 1e-9;
+    }
+    tk->fake_done = t + cost;
+    return TBR_OK;
+  }
+  hipStream_t st = tk->stream;
+  int item = 0;
+  for (size_t j = 0; j < take.size(); ++j) {
+    Request& r = s->requests[take[j]];
+    const Program& pg = s->programs[r.req.program_id];
+    float* pbase = reinterpret_cast<float*>(s->base + pg.off);
+    const int n = pg.n, k = pg.k;
+    KProgram kp{n, k, pbase, pbase + n, pbase + 2 * n, pbase + 3 * n, pbase + 4 * n,
+                pbase + 5 * n, pbase + 5 * n + (size_t)n * k};
+    // default 0.7 pixel, rounded once from double as tbr_render callers do
+    float tau_min = r.req.tau_min > 0.f ? r.req.tau_min : (float)(0.7 / (double)r.req.width);
+    KOpts ko{r.req.tau, tau_min, r.req.tau_c, r.req.eps_floor};
+    StrokeRec* recs = reinterpret_cast<StrokeRec*>(s->base + r.rec_off);
+    int nb = std::max(1, (n + 255) / 256);
+    k_stroke_prep<<<nb, 256, 0, st>>>(kp, ko, recs, nullptr);
+    ServeDesc d{};
+    d.recs = recs;
+    d.palette = kp.palette;
+    d.rgb = r.req.rgb;
+    d.label = r.req.label;
+    d.owner = r.req.owner;
+    d.n = n;
+    d.width = r.req.width;
+    d.height = r.req.height;
+    d.tiles_x = (r.req.width + 15) / 16;
+    d.soft = r.req.mode == TBR_SOFT ? 1 : 0;
+    tk->h_desc[j] = d;
+    for (int q = 0; q < r.tiles; ++q) tk->h_items[item++] = make_uint2((unsigned)j, (unsigned)q);
+    r.state = kRunning;
+    r.t_start = t;
+  }
+  ServeDesc* d_desc = reinterpret_cast<ServeDesc*>(s->base + tk->desc_off);
+  uint2* d_items = reinterpret_cast<uint2*>(s->base + tk->item_off);
+  int* d_cursor = reinterpret_cast<int*>(s->base + tk->cursor_off);
+  hipError_t e = hipMemcpyAsync(d_desc, tk->h_desc, take.size() * sizeof(ServeDesc),
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_items, tk->h_items, (size_t)n_items * sizeof(uint2),
+                       hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return sfail(TBR_E_DEVICE, "serve copy: %s", hipGetErrorString(e));
+  k_fill_i32<<<1, 64, 0, st>>>(d_cursor, 1, 0);
+  // persistent grid: at most 8 blocks per CU, never more blocks than items
+  int grid = std::min(n_items, 256 * 8);
+  k_serve<<<grid, 256, 0, st>>>(d_desc, d_items, n_items, d_cursor);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventRecord(tk->done, st);
+  if (e != hipSuccess) return sfail(TBR_E_DEVICE, "serve launch: %s", hipGetErrorString(e));
+  return TBR_OK;
+}
+
+void worker_loop(tbr_server* s) {
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (!s->stop) {
+    retire(s);
+    admit(s);
+    if (s->error.empty()) {
+      tbr_status st = launch(s);
+      if (st != TBR_OK && s->error.empty()) s->error = g_err;
+    }
+    bool busy = false;
+    for (auto& tk : s->ticks) busy |= tk.busy;
+    // sleep briefly while launches run; wake at once on submit / stop
+    s->cv.wait_for(lk, std::chrono::microseconds(busy ? 50 : 2000));
+  }
+}
+
+tbr_status check_serve_opts(const tbr_serve_opts* o) {
+  if (!o) return sfail(TBR_E_INVALID, "opts is NULL");
+  if (o->max_slots < 1 || o->max_queue < 1 || o->max_tick_items < 1)
+    return sfail(TBR_E_INVALID, "max_slots, max_queue and max_tick_items must be >= 1");
+  if (o->streams < 1 || o->streams > 4) return sfail(TBR_E_INVALID, "streams must be 1..4");
+  if (!o->fake_device && (!o->arena || o->arena_bytes == 0))
+    return sfail(TBR_E_INVALID, "arena is NULL or empty");
+  if (o->fake_device && !(o->fake_ns_per_pixel_stroke >= 0.f))
+    return sfail(TBR_E_INVALID, "fake_ns_per_pixel_stroke must be >= 0");
+  return TBR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tbr_serve_tick_bytes(const tbr_serve_opts* opts) {
+  if (!opts || opts->max_slots < 1 || opts->max_tick_items < 1) return 0;
+  return align_up((size_t)opts->max_slots * sizeof(ServeDesc)) +
+         align_up((size_t)opts->max_tick_items * sizeof(uint2)) + kAlign;
+}
+
+size_t tbr_serve_program_bytes(int32_t n_strokes, int32_t n_palette) {
+  if (n_strokes < 0 || n_palette < 1) return 0;
+  return program_bytes(n_strokes, n_palette);
+}
+
+size_t tbr_serve_request_bytes(int32_t n_strokes) {
+  if (n_strokes < 0) return 0;
+  return record_bytes(n_strokes);
+}
+
+tbr_status tbr_serve_create(const tbr_serve_opts* opts, tbr_server** out) {
+  tbr_status st;
+  if ((st = check_serve_opts(opts))) return st;
+  if (!out) return sfail(TBR_E_INVALID, "out is NULL");
+  tbr_server* s = new tbr_server();
+  s->opts = *opts;
+  s->base = static_cast<char*>(opts->arena);
+  s->arena.init(opts->arena_bytes);
+  s->ticks.resize(opts->streams);
+  const size_t tick_bytes = tbr_serve_tick_bytes(opts);
+  for (auto& tk : s->ticks) {
+    size_t off;
+    if (!s->arena.alloc(tick_bytes, &off)) {
+      tbr_serve_destroy(s);
+      return sfail(TBR_E_NOMEM, "arena too small for %d launch buffers", opts->streams);
+    }
+    tk.desc_off = off;
+    tk.item_off = off + align_up((size_t)opts->max_slots * sizeof(ServeDesc));
+    tk.cursor_off = tk.item_off + align_up((size_t)opts->max_tick_items * sizeof(uint2));
+    if (!opts->fake_device) {
+      hipError_t e = hipStreamCreateWithFlags(&tk.stream, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&tk.done, hipEventDisableTiming);
+      if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&tk.h_desc),
+                          (size_t)opts->max_slots * sizeof(ServeDesc), hipHostMallocDefault);
+      if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&tk.h_items),
+                          (size_t)opts->max_tick_items * sizeof(uint2), hipHostMallocDefault);
+      if (e != hipSuccess) {
+        tbr_serve_destroy(s);
+        return sfail(TBR_E_DEVICE, "serve create: %s", hipGetErrorString(e));
+      }
+    }
+  }
+  s->worker = std::thread(worker_loop, s);
+  *out = s;
+  return TBR_OK;
+}
+
+tbr_status tbr_serve_register_program(tbr_server* s, const tbr_program* p, uint64_t* program_id) {
+  if (!s || !p || !program_id) return sfail(TBR_E_INVALID, "null argument");
+  if (p->n_strokes < 0 || p->n_palette < 1 || p->n_palette > 64)
+    return sfail(TBR_E_INVALID, "n_strokes %d / n_palette %d out of range", p->n_strokes,
+                 p->n_palette);
+  if (!s->opts.fake_device &&
+      (!p->palette || (p->n_strokes > 0 && (!p->cx || !p->cy || !p->angle || !p->length ||
+                                             !p->half_width || !p->logits))))
+    return sfail(TBR_E_INVALID, "a program array is NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  Program pg;
+  pg.n = p->n_strokes;
+  pg.k = p->n_palette;
+  pg.bytes = program_bytes(pg.n, pg.k);
+  if (!s->arena.alloc(pg.bytes, &pg.off))
+    return sfail(TBR_E_NOMEM, "arena cannot hold a %d-stroke program", pg.n);
+  if (!s->opts.fake_device) {
+    const int n = pg.n, k = pg.k;
+    float* dst = reinterpret_cast<float*>(s->base + pg.off);
+    const float* srcs[7] = {p->cx, p->cy, p->angle, p->length, p->half_width, p->logits, p->palette};
+    size_t cnt[7] = {(size_t)n, (size_t)n, (size_t)n, (size_t)n, (size_t)n, (size_t)n * k,
+                     (size_t)3 * k};
+    hipError_t e = hipSuccess;
+    for (int f = 0; f < 7 && e == hipSuccess; ++f) {
+      if (cnt[f]) e = hipMemcpy(dst, srcs[f], cnt[f] * sizeof(float), hipMemcpyDeviceToDevice);
+      dst += cnt[f];
+    }
+    if (e != hipSuccess) {
+      s->arena.release(pg.off, pg.bytes);
+      return sfail(TBR_E_DEVICE, "register copy: %s", hipGetErrorString(e));
+    }
+  }
+  *program_id = s->next_program++;
+  s->programs[*program_id] = pg;
+  return TBR_OK;
+}
+
+tbr_status tbr_serve_submit(tbr_server* s, const tbr_request* req, uint64_t* ticket) {
+  if (!s || !req || !ticket) return sfail(TBR_E_INVALID, "null argument");
+  if (req->mode != TBR_SOFT && req->mode != TBR_HARD)
+    return sfail(TBR_E_INVALID, "mode must be TBR_SOFT or TBR_HARD");
+  if (req->width < 1 || req->width > 16384 || req->height < 1 || req->height > 16384)
+    return sfail(TBR_E_INVALID, "canvas %dx%d outside 1..16384", req->width, req->height);
+  if (!(req->tau >= 0.f) || !(req->tau_c >= 0.f) || !(req->eps_floor > 0.f))
+    return sfail(TBR_E_INVALID, "tau, tau_c must be >= 0 and eps_floor > 0");
+  if (!s->opts.fake_device) {
+    if (req->mode == TBR_SOFT && !req->rgb) return sfail(TBR_E_INVALID, "soft request without rgb");
+    if (req->mode == TBR_HARD && !req->rgb && !req->label && !req->owner)
+      return sfail(TBR_E_INVALID, "hard request without any output");
+  }
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (!s->error.empty()) return sfail(TBR_E_DEVICE, "server failed: %s", s->error.c_str());
+  auto pit = s->programs.find(req->program_id);
+  if (pit == s->programs.end()) return sfail(TBR_E_NOTFOUND, "unknown program id");
+  Request r;
+  r.req = *req;
+  r.n = pit->second.n;
+  r.k = pit->second.k;
+  r.rec_bytes = record_bytes(r.n);
+  r.tiles = tiles_of(*req);
+  if (r.tiles > s->opts.max_tick_items)
+    return sfail(TBR_E_NOMEM, "request has %d tiles > max_tick_items %d", r.tiles,
+                 s->opts.max_tick_items);
+  if (align_up(r.rec_bytes) > s->arena.size()) return sfail(TBR_E_NOMEM, "request exceeds arena");
+  if ((int)s->queue.size() >= s->opts.max_queue) return sfail(TBR_E_CAPACITY, "queue full");
+  r.ticket = s->next_ticket++;
+  r.t_submit = now_s();
+  s->requests[r.ticket] = r;
+  s->queue.push_back(r.ticket);
+  ++s->stats.submitted;
+  *ticket = r.ticket;
+  lk.unlock();
+  s->cv.notify_one();
+  return TBR_OK;
+}
+
+tbr_status tbr_serve_poll(tbr_server* s, uint64_t ticket, tbr_result* out) {
+  if (!s || !out) return sfail(TBR_E_INVALID, "null argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->requests.find(ticket);
+  if (it == s->requests.end()) return sfail(TBR_E_NOTFOUND, "unknown ticket");
+  const Request& r = it->second;
+  out->t_submit = r.t_submit;
+  out->t_admit = r.t_admit;
+  out->t_start = r.t_start;
+  out->t_done = r.t_done;
+  out->pixel_strokes = (int64_t)r.req.width * r.req.height * r.n;
+  if (r.state == kDone) {
+    out->status = TBR_OK;
+    s->requests.erase(it);
+    return TBR_OK;
+  }
+  if (r.state == kCancelled) {
+    out->status = TBR_E_CANCELLED;
+    s->requests.erase(it);
+    return TBR_E_CANCELLED;
+  }
+  if (!s->error.empty()) {
+    out->status = TBR_E_DEVICE;
+    return sfail(TBR_E_DEVICE, "server failed: %s", s->error.c_str());
+  }
+  out->status = TBR_PENDING;
+  return TBR_PENDING;
+}
+
+tbr_status tbr_serve_cancel(tbr_server* s, uint64_t ticket) {
+  if (!s) return sfail(TBR_E_INVALID, "null argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->requests.find(ticket);
+  if (it == s->requests.end()) return sfail(TBR_E_NOTFOUND, "unknown ticket");
+  if (it->second.state != kQueued) return TBR_PENDING;  // already admitted: runs to completion
+  auto q = std::find(s->queue.begin(), s->queue.end(), ticket);
+  if (q != s->queue.end()) s->queue.erase(q);
+  it->second.state = kCancelled;
+  ++s->stats.cancelled;
+  return TBR_OK;
+}
+
+tbr_status tbr_serve_get_stats(tbr_server* s, tbr_serve_stats* out) {
+  if (!s || !out) return sfail(TBR_E_INVALID, "null argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  *out = s->stats;
+  out->queued = (int64_t)s->queue.size();
+  out->in_flight = s->admitted;
+  out->arena_used = s->arena.used();
+  out->arena_bytes = s->arena.size();
+  return TBR_OK;
+}
+
+void tbr_serve_destroy(tbr_server* s) {
+  if (!s) return;
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  for (auto& tk : s->ticks) {
+    if (tk.stream) (void)hipStreamSynchronize(tk.stream);
+    if (tk.done) (void)hipEventDestroy(tk.done);
+    if (tk.stream) (void)hipStreamDestroy(tk.stream);
+    if (tk.h_desc) (void)hipHostFree(tk.h_desc);
+    if (tk.h_items) (void)hipHostFree(tk.h_items);
+  }
+  delete s;
+}
+
+double tbr_serve_now(void) { return now_s(); }
+
+}  // extern "C"

@@ -63,7 +63,11 @@ def test_adam_update_matches_torch():
         for j in range(len(lrs)):
             ref[j].grad = gr[j:j + 1].clone()
         opt.step()
-        with torch.no_grad():  # the fit step projects the palette into [0, 1]
+        with torch.no_grad():  # the fit step's projections after each update
+            for r in ref[4 * n:5 * n]:
+                r.clamp_(adam.r_lo, adam.r_hi)
+            for r in ref[3 * n:4 * n]:
+                r.clamp_(-adam.l_max, adam.l_max)
             for r in ref[len(lrs) - 3 * k:]:
                 r.clamp_(0.0, 1.0)
         want = torch.cat([r.detach() for r in ref])

@@ -1,0 +1,102 @@
+"""Host-only checks of the serving scheduler (fake executor: no GPU work):
+FIFO admission by slots and arena bytes, queue capacity, cancellation, and
+that every request completes exactly once."""
+
+import ctypes as C
+import time
+
+import pytest
+
+from paper_2609_08722_amd import _lib as L
+from paper_2609_08722_amd import api, synth
+
+
+def wait_all(srv, tickets, timeout=10.0):
+    done, t0 = {}, time.time()
+    while len(done) < len(tickets) and time.time() - t0 < timeout:
+        for t in tickets:
+            if t not in done:
+                r = srv.poll(t)
+                if r is not None:
+                    done[t] = r
+        time.sleep(0.001)
+    return done
+
+
+def test_requests_complete_in_fifo_admission_order():
+    srv = api.Server(arena_bytes=64 << 20, max_slots=4, fake_device=True,
+                     fake_ns_per_pixel_stroke=2e-3)
+    pid = srv.register(synth.make_program(500, 8, 0))
+    tickets = [srv.submit(pid, "soft" if j % 2 else "hard", 256, 256) for j in range(20)]
+    done = wait_all(srv, tickets)
+    assert len(done) == 20 and all(r["status"] == L.TBR_OK for r in done.values())
+    admits = [done[t]["t_admit"] for t in tickets]
+    assert admits == sorted(admits)  # FIFO admission
+    for r in done.values():
+        assert r["t_submit"] <= r["t_admit"] <= r["t_start"] <= r["t_done"]
+        assert r["pixel_strokes"] == 256 * 256 * 500
+    st = srv.stats()
+    assert st["completed"] == 20 and st["in_flight"] == 0 and st["queued"] == 0
+    with pytest.raises(L.TbrError):
+        srv.poll(tickets[0])
+    srv.close()
+
+
+def test_admission_limited_by_arena_bytes():
+    # arena holds the launch buffers, the program and ~2 requests' records
+    n = 4000
+    rec = L.load().tbr_serve_request_bytes(n)
+    prog_bytes = L.load().tbr_serve_program_bytes(n, 8)
+    probe = L.ServeOpts(None, 0, 16, 4096, 8192, 1, 1, 0.0)
+    tick = L.load().tbr_serve_tick_bytes(C.byref(probe))
+    srv = api.Server(arena_bytes=tick + prog_bytes + 2 * rec + rec // 2, max_slots=16,
+                     max_tick_items=8192, streams=1, fake_device=True,
+                     fake_ns_per_pixel_stroke=1e-3)
+    pid = srv.register(synth.make_program(n, 8, 1))
+    tickets = [srv.submit(pid, "soft", 128, 128) for _ in range(12)]
+    peak = 0
+    for _ in range(200):
+        peak = max(peak, srv.stats()["in_flight"])
+        time.sleep(0.0005)
+    assert 1 <= peak <= 2  # bounded by arena bytes, not by the 16 slots
+    done = wait_all(srv, tickets)
+    assert len(done) == 12
+    # everything but the program and the launch buffers is released again
+    assert srv.stats()["arena_used"] == prog_bytes + tick
+    srv.close()
+
+
+def test_queue_capacity_and_cancel():
+    srv = api.Server(arena_bytes=64 << 20, max_slots=1, max_queue=3, streams=1, fake_device=True,
+                     fake_ns_per_pixel_stroke=50.0)  # slow: requests stay queued
+    pid = srv.register(synth.make_program(1000, 8, 2))
+    t0 = srv.submit(pid, "soft", 512, 512)  # admitted and running for ~13 s (modelled)
+    time.sleep(0.01)
+    queued = [srv.submit(pid, "hard", 64, 64) for _ in range(3)]
+    with pytest.raises(L.TbrError) as e:
+        srv.submit(pid, "hard", 64, 64)
+    assert e.value.status == L.TBR_E_CAPACITY
+    assert srv.cancel(queued[1]) == L.TBR_OK
+    assert srv.cancel(t0) == L.TBR_PENDING  # already admitted: runs to completion
+    r = srv.poll(queued[1])
+    assert r["status"] == L.TBR_E_CANCELLED
+    assert srv.stats()["cancelled"] == 1
+    srv.close()  # destroy with work in flight must not hang
+
+
+def test_invalid_requests_rejected():
+    srv = api.Server(arena_bytes=16 << 20, fake_device=True)
+    pid = srv.register(synth.make_program(10, 4, 3))
+    for kw in (dict(width=0), dict(height=20000), dict(eps=0.0), dict(tau=-1.0)):
+        args = dict(width=64, height=64)
+        args.update(kw)
+        with pytest.raises(L.TbrError) as e:
+            srv.submit(pid, "soft", args.pop("width"), args.pop("height"), **args)
+        assert e.value.status == L.TBR_E_INVALID
+    with pytest.raises(L.TbrError) as e:
+        srv.submit(pid + 100, "soft", 64, 64)
+    assert e.value.status == L.TBR_E_NOTFOUND
+    with pytest.raises(L.TbrError) as e:  # more tiles than one launch can hold
+        srv.submit(pid, "soft", 16384, 16384)
+    assert e.value.status == L.TBR_E_NOMEM
+    srv.close()
