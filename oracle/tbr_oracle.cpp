@@ -225,7 +225,15 @@ template <class T>
 T soft_alpha(const T& sigma, const T& r, double tau, double tau_min) {
   T wd = val(r) * tau > tau_min ? tau * r : T(tau_min);
   T z = (r - sigma) / wd;
-  T a = 1.0 / (1.0 + m_exp(-z));
+  // The logistic function, written so that the exponential never overflows
+  // (far pixels reach z < -709): e^z / (1 + e^z) for z < 0.
+  T a;
+  if (val(z) >= 0) {
+    a = 1.0 / (1.0 + m_exp(-z));
+  } else {
+    T ez = m_exp(z);
+    a = ez / (1.0 + ez);
+  }
   if (val(a) > kAlphaMax) a = T(kAlphaMax);
   return a;
 }

@@ -23,14 +23,20 @@ def close(a, b, rtol, group, atol=0.0):
     return np.abs(a - b) <= rtol * (np.abs(b) + 0.01 * rms) + atol
 
 
-@pytest.mark.parametrize("tau,tau_c,transport", [(1e-3, 1.0, True), (0.35, 0.5, True),
-                                                  (1e-3, 1.0, False)])
-def test_gradient_matches_central_differences(orc, tau, tau_c, transport):
+# The last case has a floor width so small that far pixels reach
+# (r - sigma) / w_d < -709, where exp(-z) overflows in FP64: the coverage
+# and its derivative must still come out as the limits 0, not NaN.
+@pytest.mark.parametrize("tau,tau_c,transport,tau_min", [(1e-3, 1.0, True, None),
+                                                          (0.35, 0.5, True, None),
+                                                          (1e-3, 1.0, False, None),
+                                                          (1e-3, 1.0, True, 1e-4)])
+def test_gradient_matches_central_differences(orc, tau, tau_c, transport, tau_min):
     W = H = 24
     prog = synth.make_program(12, 4, 21, synth.DIST_SMALL, beta=2.0, dtype=np.float64)
     prog["half_width"] = prog["half_width"] * 3  # larger strokes: more interaction
     target_prog = synth.make_program(12, 4, 22, synth.DIST_SMALL, dtype=np.float64)
-    kw = dict(tau=tau, tau_min=0.7 / W, tau_c=tau_c, transport=transport)
+    kw = dict(tau=tau, tau_min=0.7 / W if tau_min is None else tau_min, tau_c=tau_c,
+              transport=transport)
     target = orc.render(target_prog, W, H, hard=False, **kw)["soft"]
     loss, seed = loss_and_seed(orc, prog, W, H, target, **kw)
     g = orc.backward(prog, W, H, seed, **kw)
