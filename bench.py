@@ -105,6 +105,52 @@ def ckpt_baseline(w, dprog, target, every=50, steps=2):
             "loss": float(loss), "impl": "PyTorch ops + torch.utils.checkpoint, FP32"}
 
 
+def batched_fit_benchmark(steps=3):
+    """The 8-job uneven batch: fused multi-job step vs the same jobs stepped
+    one after another with tbr_fit_step."""
+    import torch
+    from paper_2609_08722_amd import api, synth
+    states, states_seq, targets, work = [], [], [], 0
+    for j in range(len(synth.BATCH_JOBS)):
+        w = synth.batch_job(j)
+        prog = api.to_device(synth.workload_program(w))
+        tgt = api.render(api.to_device(synth.workload_program(w, seed=w.target_seed)),
+                         api.Opts(w.width, w.height), "hard")["rgb"]
+        opts = api.Opts(w.width, w.height, tau=w.tau, tau_c=w.tau_c, ckpt=w.ckpt, side_slots=28)
+        adam = api.Adam(r_lo=0.002, r_hi=0.02, l_max=0.08)
+        states.append(api.FitState(prog, opts, adam))
+        states_seq.append(api.FitState({k: v.clone() for k, v in prog.items()}, opts, adam))
+        targets.append(tgt)
+        work += w.pixels * w.n_strokes
+    multi = api.MultiFit(states)
+    multi.step(targets)
+    recs = multi.tape_records()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        multi.step(targets)
+    torch.cuda.synchronize()
+    t_multi = (time.perf_counter() - t0) / steps
+    for f, t in zip(states_seq, targets):
+        f.step(t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for f, t in zip(states_seq, targets):
+            f.step(t)
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / steps
+    same = all(torch.equal(a.params, b.params) for a, b in zip(states, states_seq))
+    del multi, states, states_seq
+    torch.cuda.empty_cache()
+    return {"jobs": [f"{s}x{s}x{n}" for s, n in synth.BATCH_JOBS],
+            "pixel_strokes_per_step": work,
+            "fused_ms_per_step": t_multi * 1e3, "fused_pixel_strokes_per_s": work / t_multi,
+            "sequential_ms_per_step": t_seq * 1e3,
+            "sequential_pixel_strokes_per_s": work / t_seq,
+            "side_table_max_records": recs, "fused_equals_sequential": bool(same)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +160,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ckpt-baseline", action="store_true",
                     help="skip the checkpointed-autograd PyTorch baseline")
+    ap.add_argument("--no-batched-fit", action="store_true",
+                    help="skip the 8-job batched fit comparison")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="length of the Poisson serving replay (0 = skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -251,10 +299,13 @@ def main():
     }
     if not args.no_ckpt_baseline:
         out["ckpt_autograd_baseline"] = ckpt_baseline(w, dprog, target)
+    del fit
+    torch.cuda.empty_cache()
+    if not args.no_batched_fit:
+        out["batched_fit"] = batched_fit_benchmark()
+        log(f"[bench] batched fit: {out['batched_fit']}")
     if args.serve_seconds > 0:
         from paper_2609_08722_amd.serve_driver import serving_benchmark
-        del fit
-        torch.cuda.empty_cache()
         out["serving"] = serving_benchmark(duration=args.serve_seconds, warmup=1.0)
         log(f"[bench] serving: {out['serving']}")
     if not args.no_cpu_baseline:

@@ -167,6 +167,38 @@ tbr_status tbr_fit_step(int32_t n_strokes, int32_t n_palette, float* params, flo
                         const tbr_render_opts* opts, const float* target_rgb, float* loss,
                         void* workspace, size_t workspace_bytes, void* stream);
 
+/* One job of a batched fit: its own program (packed params, as in
+ * tbr_fit_step), Adam state, target, options and step settings. */
+typedef struct tbr_fit_job {
+  int32_t n_strokes, n_palette;
+  float* params;            /* packed [cx|cy|angle|length|half_width|logits|palette], in place */
+  float* grads;             /* packed gradient, written (may be NULL) */
+  float* adam_m;
+  float* adam_v;
+  const float* target_rgb;  /* [H*W*3] */
+  float* loss;              /* device scalar, written */
+  tbr_render_opts opts;
+  tbr_adam_opts adam;
+} tbr_fit_job;
+
+/* Workspace bytes for tbr_fit_multi_step over these jobs (1..16 jobs). */
+size_t tbr_fit_multi_workspace_bytes(const tbr_fit_job* jobs, int32_t n_jobs);
+
+/* One fit step (as tbr_fit_step) for every job, with the soft forward and
+ * the replay adjoint of ALL jobs fused into one persistent launch: blocks
+ * take (job, 16x16 tile) items, largest jobs first, and per tile run the
+ * forward with tape, the L2 seed and the replay of that tile. Reductions and
+ * Adam follow per job. Each job's results equal its own tbr_fit_step
+ * (partial rows are indexed by tile, so the summation order is fixed). */
+tbr_status tbr_fit_multi_step(const tbr_fit_job* jobs, int32_t n_jobs, void* workspace,
+                              size_t workspace_bytes, void* stream);
+
+/* Side-table high-water marks of the last multi step, per job
+ * (max_records[n_jobs]). SYNCHRONISES the stream; TBR_E_OVERFLOW if any job
+ * overflowed its side_slots. */
+tbr_status tbr_fit_multi_records(const tbr_fit_job* jobs, int32_t n_jobs, const void* workspace,
+                                 size_t workspace_bytes, int32_t* max_records, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of replay requests (the forward render above,
  * for many programs, resolutions and modes arriving over time).
@@ -262,8 +294,8 @@ void tbr_serve_destroy(tbr_server* server);
 double tbr_serve_now(void);
 
 /* Optional timing hook for benchmarks. While set on the calling thread,
- * every launch of the kernel named `kernel` ("trace_soft", "trace_hard" or
- * "replay") made by a tbr_* call on this thread is bracketed by
+ * every launch of the kernel named `kernel` ("trace_soft", "trace_hard",
+ * "replay" or "fit_fused") made by a tbr_* call on this thread is bracketed by
  * hipEventRecord(begin) / hipEventRecord(end) on that call's stream (with
  * several launches, the last pair stands). begin and end are hipEvent_t
  * handles owned by the caller. kernel = NULL clears the hook. */

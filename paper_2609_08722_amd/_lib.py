@@ -51,6 +51,13 @@ class AdamOpts(C.Structure):
                 ("step", C.c_int32)]
 
 
+class FitJob(C.Structure):
+    _fields_ = [("n_strokes", C.c_int32), ("n_palette", C.c_int32), ("params", C.c_void_p),
+                ("grads", C.c_void_p), ("adam_m", C.c_void_p), ("adam_v", C.c_void_p),
+                ("target_rgb", C.c_void_p), ("loss", C.c_void_p), ("opts", RenderOpts),
+                ("adam", AdamOpts)]
+
+
 class ServeOpts(C.Structure):
     _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("max_slots", C.c_int32),
                 ("max_queue", C.c_int32), ("max_tick_items", C.c_int32), ("streams", C.c_int32),
@@ -87,6 +94,9 @@ SIGNATURES = {
     "tbr_fit_workspace_bytes": (_sz, [_vp, _i32, _i32]),
     "tbr_fit_step": (_i32, [_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "tbr_set_timing_events": (_i32, [C.c_char_p, _vp, _vp]),
+    "tbr_fit_multi_workspace_bytes": (_sz, [_vp, _i32]),
+    "tbr_fit_multi_step": (_i32, [_vp, _i32, _vp, _sz, _vp]),
+    "tbr_fit_multi_records": (_i32, [_vp, _i32, _vp, _sz, _vp, _vp]),
     "tbr_serve_program_bytes": (_sz, [_i32, _i32]),
     "tbr_serve_request_bytes": (_sz, [_i32]),
     "tbr_serve_tick_bytes": (_sz, [_vp]),

@@ -261,6 +261,52 @@ class FitState:
         self._alloc()
 
 
+class MultiFit:
+    """Several FitStates stepped together by tbr_fit_multi_step: their soft
+    forwards and replay adjoints share one fused persistent launch."""
+
+    def __init__(self, states: list):
+        self.states = states
+        self._alloc()
+
+    def _jobs(self):
+        arr = (L.FitJob * len(self.states))()
+        for j, f in enumerate(self.states):
+            a = f.adam
+            arr[j] = L.FitJob(f.n, f.k, _ptr(f.params), _ptr(f.grads), _ptr(f.m), _ptr(f.v),
+                              _ptr(f._target), _ptr(f.loss), f.opts.c(),
+                              L.AdamOpts(a.lr_centre, a.lr_angle, a.lr_length, a.lr_width,
+                                         a.lr_logits, a.lr_palette, a.beta1, a.beta2, a.eps,
+                                         a.r_lo, a.r_hi, a.l_max, max(f.step_index, 1)))
+        return arr
+
+    def _alloc(self):
+        for f in self.states:
+            f._target = getattr(f, "_target", None)
+        lib = L.load()
+        jobs = self._jobs()
+        self.nbytes = lib.tbr_fit_multi_workspace_bytes(jobs, len(self.states))
+        self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.states[0].params.device)
+
+    def step(self, targets: list) -> list:
+        lib = L.load()
+        for f, t in zip(self.states, targets):
+            f._target = t.to(torch.float32).contiguous()
+            f.step_index += 1
+        jobs = self._jobs()
+        L.check(lib.tbr_fit_multi_step(jobs, len(self.states), _ptr(self.ws), self.nbytes,
+                                       _stream()))
+        return [f.loss for f in self.states]
+
+    def tape_records(self) -> list:
+        lib = L.load()
+        jobs = self._jobs()
+        out = (C.c_int32 * len(self.states))()
+        L.check(lib.tbr_fit_multi_records(jobs, len(self.states), _ptr(self.ws), self.nbytes,
+                                          out, _stream()))
+        return list(out)
+
+
 class Server:
     """Continuous-batching server of replay requests (tbr_serve_*).
 

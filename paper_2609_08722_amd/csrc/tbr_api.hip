@@ -7,7 +7,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "tbr.h"
 #include "tbr_kernels.hpp"
@@ -199,14 +201,35 @@ tbr_status launch_prep(const tbr_program* p, const tbr_render_opts* o, StrokeRec
   return check_launch("stroke_prep");
 }
 
+// Deterministic reduction of the tiles' partial rows and the chain rule to
+// the program arrays (shared by the backward and both fit steps).
+tbr_status launch_reduce(const tbr_program* p, const tbr_render_opts* o, const tbr_program_grad* g,
+                         char* ws, const BackLayout& BL, hipStream_t st) {
+  const int n = p->n_strokes;
+  float* partial = reinterpret_cast<float*>(ws + BL.partial);
+  double* groups = reinterpret_cast<double*>(ws + BL.groups);
+  float* gcol = reinterpret_cast<float*>(ws + BL.gcol);
+  int rows8 = (n + 1) * 8;
+  int nt = (int)n_tiles(o);
+  int tpg = (nt + kGroups - 1) / kGroups;
+  k_sum_tiles<<<dim3((rows8 + 255) / 256, kGroups), 256, 0, st>>>(partial, rows8, nt, tpg, groups);
+  tbr_status s = check_launch("sum_tiles");
+  if (s) return s;
+  KGrad kg{g->cx, g->cy, g->angle, g->length, g->half_width, g->logits, g->palette};
+  float* pal_terms = reinterpret_cast<float*>(ws + BL.pal_terms);
+  k_finalize<<<(n + 1 + 255) / 256, 256, 0, st>>>(groups, kGroups, kprog(p), kopts(o), kg, gcol,
+                                                  pal_terms);
+  if ((s = check_launch("finalize"))) return s;
+  k_palette_grad<<<p->n_palette * 3, 256, 0, st>>>(pal_terms, n, p->n_palette, gcol, g->palette);
+  return check_launch("palette_grad");
+}
+
 tbr_status launch_backward(const tbr_program* p, const tbr_render_opts* o, const char* tape_ws,
                            const RenderLayout& RL, const float* grad_rgb, const tbr_program_grad* g,
                            char* ws, const BackLayout& BL, hipStream_t st) {
   const int n = p->n_strokes;
   KTape t = ktape(const_cast<char*>(tape_ws), RL, o, true);
   float* partial = reinterpret_cast<float*>(ws + BL.partial);
-  double* groups = reinterpret_cast<double*>(ws + BL.groups);
-  float* gcol = reinterpret_cast<float*>(ws + BL.gcol);
   const StrokeRec* recs = reinterpret_cast<const StrokeRec*>(tape_ws + RL.recs);
   dim3 grid(tiles_x(o), tiles_y(o));
   {
@@ -215,18 +238,32 @@ tbr_status launch_backward(const tbr_program* p, const tbr_render_opts* o, const
   }
   tbr_status s = check_launch("replay");
   if (s) return s;
-  int rows8 = (n + 1) * 8;
-  int nt = (int)n_tiles(o);
-  int tpg = (nt + kGroups - 1) / kGroups;
-  k_sum_tiles<<<dim3((rows8 + 255) / 256, kGroups), 256, 0, st>>>(partial, rows8, nt, tpg, groups);
-  if ((s = check_launch("sum_tiles"))) return s;
-  KGrad kg{g->cx, g->cy, g->angle, g->length, g->half_width, g->logits, g->palette};
-  float* pal_terms = reinterpret_cast<float*>(ws + BL.pal_terms);
-  k_finalize<<<(n + 1 + 255) / 256, 256, 0, st>>>(groups, kGroups, kprog(p), kopts(o), kg, gcol,
-                                                  pal_terms);
-  if ((s = check_launch("finalize"))) return s;
-  k_palette_grad<<<p->n_palette * 3, 256, 0, st>>>(pal_terms, n, p->n_palette, gcol, g->palette);
-  return check_launch("palette_grad");
+  return launch_reduce(p, o, g, ws, BL, st);
+}
+
+KAdam kadam(const tbr_adam_opts* adam) {
+  return KAdam{adam->lr_centre, adam->lr_angle, adam->lr_length, adam->lr_width, adam->lr_logits,
+               adam->lr_palette, adam->beta1, adam->beta2, adam->eps,
+               (float)(1.0 - std::pow((double)adam->beta1, adam->step)),
+               (float)(1.0 - std::pow((double)adam->beta2, adam->step)),
+               adam->r_lo, adam->r_hi, adam->l_max};
+}
+
+tbr_status check_adam(const tbr_adam_opts* adam) {
+  if (!adam) return fail(TBR_E_INVALID, "adam opts are NULL");
+  if (adam->step < 1) return fail(TBR_E_INVALID, "adam step must be >= 1");
+  if (!(adam->beta1 >= 0.f && adam->beta1 < 1.f && adam->beta2 >= 0.f && adam->beta2 < 1.f &&
+        adam->eps > 0.f && adam->r_lo > 0.f && adam->r_hi >= adam->r_lo && adam->l_max >= 0.f))
+    return fail(TBR_E_INVALID, "bad Adam settings");
+  return TBR_OK;
+}
+
+// Multi-job workspace: [cursor 256 B][job 0 fit layout][job 1 ...]
+size_t multi_offset(const tbr_fit_job* jobs, int j) {
+  size_t off = kAlign;
+  for (int q = 0; q < j; ++q)
+    off = align_up(off + fit_layout(&jobs[q].opts, jobs[q].n_strokes, jobs[q].n_palette).total);
+  return off;
 }
 
 }  // namespace
@@ -338,10 +375,7 @@ tbr_status tbr_fit_step(int32_t n_strokes, int32_t n_palette, float* params, flo
   if (!params || !adam_m || !adam_v || !adam || !target_rgb || !loss || !workspace)
     return fail(TBR_E_INVALID, "null argument");
   if ((s = check_opts(opts, true, true))) return s;
-  if (adam->step < 1) return fail(TBR_E_INVALID, "adam step must be >= 1");
-  if (!(adam->beta1 >= 0.f && adam->beta1 < 1.f && adam->beta2 >= 0.f && adam->beta2 < 1.f &&
-        adam->eps > 0.f && adam->r_lo > 0.f && adam->r_hi >= adam->r_lo && adam->l_max >= 0.f))
-    return fail(TBR_E_INVALID, "bad Adam settings");
+  if ((s = check_adam(adam))) return s;
   FitLayout FL = fit_layout(opts, n_strokes, n_palette);
   if (workspace_bytes < FL.total)
     return fail(TBR_E_INVALID, "workspace %zu bytes < required %zu", workspace_bytes, FL.total);
@@ -371,14 +405,126 @@ tbr_status tbr_fit_step(int32_t n_strokes, int32_t n_palette, float* params, flo
                                   loss);
   if ((s = check_launch("loss_final"))) return s;
   if ((s = launch_backward(&prog, opts, rws, FL.r, seed, &pg, bws, FL.b, st))) return s;
-  KAdam a{adam->lr_centre, adam->lr_angle, adam->lr_length, adam->lr_width, adam->lr_logits,
-          adam->lr_palette, adam->beta1, adam->beta2, adam->eps,
-          (float)(1.0 - std::pow((double)adam->beta1, adam->step)),
-          (float)(1.0 - std::pow((double)adam->beta2, adam->step)),
-          adam->r_lo, adam->r_hi, adam->l_max};
   int total = (int)packed_len(N, K);
-  k_adam<<<(total + 255) / 256, 256, 0, st>>>(params, g, adam_m, adam_v, N, K, a);
+  k_adam<<<(total + 255) / 256, 256, 0, st>>>(params, g, adam_m, adam_v, N, K, kadam(adam));
   return check_launch("adam");
+}
+
+size_t tbr_fit_multi_workspace_bytes(const tbr_fit_job* jobs, int32_t n_jobs) {
+  if (!jobs || n_jobs < 1 || n_jobs > kMaxFitJobs) return 0;
+  for (int j = 0; j < n_jobs; ++j)
+    if (jobs[j].n_strokes < 0 || jobs[j].n_palette < 1) return 0;
+  return multi_offset(jobs, n_jobs);
+}
+
+tbr_status tbr_fit_multi_step(const tbr_fit_job* jobs, int32_t n_jobs, void* workspace,
+                              size_t workspace_bytes, void* stream) {
+  tbr_status s;
+  if (!jobs || n_jobs < 1 || n_jobs > kMaxFitJobs)
+    return fail(TBR_E_INVALID, "n_jobs = %d outside 1..%d", n_jobs, kMaxFitJobs);
+  if (!workspace) return fail(TBR_E_INVALID, "workspace is NULL");
+  for (int j = 0; j < n_jobs; ++j) {
+    const tbr_fit_job& J = jobs[j];
+    if (J.n_strokes < 0 || J.n_palette < 1 || J.n_palette > 64)
+      return fail(TBR_E_INVALID, "job %d: n_strokes %d / n_palette %d out of range", j,
+                  J.n_strokes, J.n_palette);
+    if (!J.params || !J.adam_m || !J.adam_v || !J.target_rgb || !J.loss)
+      return fail(TBR_E_INVALID, "job %d: null argument", j);
+    if ((s = check_opts(&J.opts, true, true))) return s;
+    if ((s = check_adam(&J.adam))) return s;
+  }
+  const size_t need = multi_offset(jobs, n_jobs);
+  if (workspace_bytes < need)
+    return fail(TBR_E_INVALID, "workspace %zu bytes < required %zu", workspace_bytes, need);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  // jobs in decreasing cost order, so the largest jobs' tiles are taken first
+  int order[kMaxFitJobs];
+  for (int j = 0; j < n_jobs; ++j) order[j] = j;
+  std::sort(order, order + n_jobs, [&](int a, int b) {
+    double ca = (double)n_pixels(&jobs[a].opts) * jobs[a].n_strokes;
+    double cb = (double)n_pixels(&jobs[b].opts) * jobs[b].n_strokes;
+    return ca > cb || (ca == cb && a < b);
+  });
+  FitJobsK K{};
+  K.n_jobs = n_jobs;
+  int items = 0;
+  std::vector<tbr_program> progs(n_jobs);
+  std::vector<tbr_program_grad> pgrads(n_jobs);
+  std::vector<FitLayout> layouts(n_jobs);
+  for (int q = 0; q < n_jobs; ++q) {
+    const int j = order[q];
+    const tbr_fit_job& J = jobs[j];
+    const int N = J.n_strokes, Kp = J.n_palette;
+    FitLayout FL = fit_layout(&J.opts, N, Kp);
+    layouts[j] = FL;
+    char* base = ws + multi_offset(jobs, j);
+    char* rws = base + FL.base_r;
+    float* g = J.grads ? J.grads : reinterpret_cast<float*>(base + FL.grads);
+    float* pr = J.params;
+    progs[j] = tbr_program{N, Kp, pr, pr + N, pr + 2 * N, pr + 3 * N, pr + 4 * N, pr + 5 * N,
+                           pr + 5 * N + (size_t)N * Kp};
+    pgrads[j] = tbr_program_grad{g, g + N, g + 2 * N, g + 3 * N, g + 4 * N, g + 5 * N,
+                                 g + 5 * N + (size_t)N * Kp};
+    StrokeRec* recs = reinterpret_cast<StrokeRec*>(rws + FL.r.recs);
+    KTape t = ktape(rws, FL.r, &J.opts, true);
+    if ((s = launch_prep(&progs[j], &J.opts, recs, t.status, st))) return s;
+    FitJobK& D = K.job[q];
+    D.recs = recs;
+    D.palette = progs[j].palette;
+    D.target = J.target_rgb;
+    D.partial = reinterpret_cast<float*>(base + FL.base_b + FL.b.partial);
+    D.loss_part = reinterpret_cast<float*>(base + FL.loss_part);
+    D.tape = t;
+    D.n = N;
+    D.width = J.opts.width;
+    D.height = J.opts.height;
+    D.tiles_x = tiles_x(&J.opts);
+    D.item0 = items;
+    items += (int)n_tiles(&J.opts);
+  }
+  K.n_items = items;
+  int* cursor = reinterpret_cast<int*>(ws);
+  k_fill_i32<<<1, 64, 0, st>>>(cursor, 1, 0);
+  if ((s = check_launch("fill"))) return s;
+  {
+    Timed tm("fit_fused", st);
+    k_fit_fused<<<std::min(items, 256 * 8), 256, 0, st>>>(K, cursor);
+  }
+  if ((s = check_launch("fit_fused"))) return s;
+  for (int j = 0; j < n_jobs; ++j) {
+    const tbr_fit_job& J = jobs[j];
+    const FitLayout& FL = layouts[j];
+    char* base = ws + multi_offset(jobs, j);
+    k_loss_final<<<1, 256, 0, st>>>(reinterpret_cast<float*>(base + FL.loss_part),
+                                    (int)n_tiles(&J.opts),
+                                    1.0f / (3.0f * (float)n_pixels(&J.opts)), J.loss);
+    if ((s = check_launch("loss_final"))) return s;
+    if ((s = launch_reduce(&progs[j], &J.opts, &pgrads[j], base + FL.base_b, FL.b, st))) return s;
+    int total = (int)packed_len(J.n_strokes, J.n_palette);
+    k_adam<<<(total + 255) / 256, 256, 0, st>>>(J.params, pgrads[j].cx, J.adam_m, J.adam_v,
+                                                J.n_strokes, J.n_palette, kadam(&J.adam));
+    if ((s = check_launch("adam"))) return s;
+  }
+  return TBR_OK;
+}
+
+tbr_status tbr_fit_multi_records(const tbr_fit_job* jobs, int32_t n_jobs, const void* workspace,
+                                 size_t workspace_bytes, int32_t* max_records, void* stream) {
+  if (!jobs || n_jobs < 1 || n_jobs > kMaxFitJobs || !workspace || !max_records)
+    return fail(TBR_E_INVALID, "null argument or bad n_jobs");
+  if (workspace_bytes < multi_offset(jobs, n_jobs)) return fail(TBR_E_INVALID, "workspace too small");
+  tbr_status worst = TBR_OK;
+  for (int j = 0; j < n_jobs; ++j) {
+    FitLayout FL = fit_layout(&jobs[j].opts, jobs[j].n_strokes, jobs[j].n_palette);
+    const char* base = static_cast<const char*>(workspace) + multi_offset(jobs, j) + FL.base_r;
+    tbr_status s = tbr_tape_records(base, FL.r.total, &jobs[j].opts, jobs[j].n_strokes,
+                                    &max_records[j], stream);
+    if (s == TBR_E_OVERFLOW) worst = s;
+    else if (s != TBR_OK) return s;
+  }
+  if (worst == TBR_E_OVERFLOW) return fail(TBR_E_OVERFLOW, "a job's side table overflowed");
+  return TBR_OK;
 }
 
 tbr_status tbr_set_timing_events(const char* kernel, void* begin, void* end) {

@@ -415,28 +415,25 @@ __device__ __forceinline__ int value_index_of_lane(int lane) {
 // ---------------------------------------------------------------------------
 constexpr int kChunk = 32;
 
-__global__ void __launch_bounds__(256)
-    k_replay(const StrokeRec* __restrict__ recs, int n, int width, int height,
-             const float* __restrict__ palette, const float* __restrict__ grad_rgb, KTape tape,
-             float* __restrict__ partial) {
-  __shared__ float lds[2][4][kChunk][8];
+// The replay of one 16x16 tile by the whole block (all 256 threads must
+// call it). lcr, lcg, lcb: this lane's dL/dR; prow: the tile's partial row
+// [n + 1][8] (row n = background colour gradient).
+__device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, int n,
+                                            const PixelId& id, int width, int height,
+                                            const float* __restrict__ palette, float lcr,
+                                            float lcg, float lcb, const KTape& tape,
+                                            float* __restrict__ prow,
+                                            float (&lds)[2][4][kChunk][8]) {
   const float bgr = palette[0], bgg = palette[1], bgb = palette[2];
-  PixelId id = pixel_of_tile(blockIdx.x, blockIdx.y, width, height);
   const int P = width * height;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int tile = blockIdx.y * gridDim.x + blockIdx.x;
-  float* prow = partial + (size_t)tile * (n + 1) * 8;
   const int k = tape.ckpt_interval;
-
-  // seed: lambda^C = dL/dR (constant along the chain), lambda^T_0 = lambda^C . c_0
-  float lcr = 0.f, lcg = 0.f, lcb = 0.f;
+  // start from the final state s_0: lambda^C = dL/dR (constant along the
+  // chain), lambda^T_0 = lambda^C . c_0, lambda^x_0 = 0
   double x = 0.5, y = 0.5;
   float tm = 1.f;
   int te = 0, top = 0, top_idx = -1;
   if (id.active) {
-    lcr = grad_rgb[3 * (size_t)id.p + 0];
-    lcg = grad_rgb[3 * (size_t)id.p + 1];
-    lcb = grad_rgb[3 * (size_t)id.p + 2];
     double2 s0 = tape.ckpt_xy[id.p];
     float2 t0 = tape.ckpt_t[id.p];
     x = s0.x;
@@ -445,6 +442,8 @@ __global__ void __launch_bounds__(256)
     te = (int)t0.y;
     top = min(tape.nrec[id.p], tape.side_slots);
     top_idx = top > 0 ? tape.side_idx[(size_t)(top - 1) * P + id.p] : -1;
+  } else {
+    lcr = lcg = lcb = 0.f;
   }
   float lt = fmaf(lcr, bgr, fmaf(lcg, bgg, lcb * bgb));
   float lx = 0.f, ly = 0.f;
@@ -453,6 +452,7 @@ __global__ void __launch_bounds__(256)
     float t0 = trans_value(tm, te);
     float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, lcr * t0, lcg * t0, lcb * t0};
     float tot = wave_total8(v, lane);
+    __syncthreads();  // lds may still be read by a previous tile of this block
     if (lane < 8) lds[0][wave][0][value_index_of_lane(lane)] = tot;
     __syncthreads();
     if (threadIdx.x < 8) {
@@ -622,6 +622,75 @@ __global__ void __launch_bounds__(256)
         prow[(size_t)(c0 + j) * 8 + vv] = s;
       }
     }
+  }
+}
+
+
+__global__ void __launch_bounds__(256)
+    k_replay(const StrokeRec* __restrict__ recs, int n, int width, int height,
+             const float* __restrict__ palette, const float* __restrict__ grad_rgb, KTape tape,
+             float* __restrict__ partial) {
+  __shared__ float lds[2][4][kChunk][8];
+  PixelId id = pixel_of_tile(blockIdx.x, blockIdx.y, width, height);
+  const int tile = blockIdx.y * gridDim.x + blockIdx.x;
+  float lcr = 0.f, lcg = 0.f, lcb = 0.f;
+  if (id.active) {
+    lcr = grad_rgb[3 * (size_t)id.p + 0];
+    lcg = grad_rgb[3 * (size_t)id.p + 1];
+    lcb = grad_rgb[3 * (size_t)id.p + 2];
+  }
+  replay_tile(recs, n, id, width, height, palette, lcr, lcg, lcb, tape,
+              partial + (size_t)tile * (n + 1) * 8, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Fused fit over several jobs: one persistent launch pulls (job, tile) items
+// through an atomic cursor (the largest jobs first). Per tile: the soft
+// forward with tape, the L2 seed dL/dR = 2 (R - I*) / (3 P) kept in
+// registers, the tile's loss partial, and at once the replay of the same
+// tile (each lane reads back only its own tape). Partial rows are indexed by
+// tile, so the order in which blocks take tiles cannot change any sum.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_fit_fused(FitJobsK jobs, int* __restrict__ cursor) {
+  __shared__ float lds[2][4][kChunk][8];
+  __shared__ float red[256];
+  __shared__ int item_s;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = atomicAdd(cursor, 1);
+    __syncthreads();
+    const int it = item_s;
+    __syncthreads();
+    if (it >= jobs.n_items) break;
+    int jb = 0;
+    while (jb + 1 < jobs.n_jobs && it >= jobs.job[jb + 1].item0) ++jb;
+    const FitJobK& J = jobs.job[jb];
+    const int tile = it - J.item0;
+    PixelId id = pixel_of_tile(tile % J.tiles_x, tile / J.tiles_x, J.width, J.height);
+    const int P = J.width * J.height;
+    SoftOut o = soft_pixel<true>(J.recs, J.n, id, J.width, J.height, J.palette, J.tape);
+    float lcr = 0.f, lcg = 0.f, lcb = 0.f, sq = 0.f;
+    if (id.active) {
+      float dr = o.cr - J.target[3 * (size_t)id.p + 0];
+      float dg = o.cg - J.target[3 * (size_t)id.p + 1];
+      float db = o.cb - J.target[3 * (size_t)id.p + 2];
+      float sc = 2.0f / (3.0f * (float)P);
+      lcr = sc * dr;
+      lcg = sc * dg;
+      lcb = sc * db;
+      sq = fmaf(dr, dr, fmaf(dg, dg, db * db));
+    }
+    int m = id.active ? o.nrec : 0;  // side-table high-water mark, one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(J.tape.status, m);
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) J.loss_part[tile] = red[0];
+    replay_tile(J.recs, J.n, id, J.width, J.height, J.palette, lcr, lcg, lcb, J.tape,
+                J.partial + (size_t)tile * (J.n + 1) * 8, lds);
   }
 }
 

@@ -52,6 +52,22 @@ struct ServeDesc {
   int pad[3];
 };
 
+// One job of the fused multi-job fit (passed by value in the kernel arguments).
+struct FitJobK {
+  const StrokeRec* recs;
+  const float* palette;
+  const float* target;  // [P*3]
+  float* partial;       // [tiles][n + 1][8]
+  float* loss_part;     // [tiles]
+  KTape tape;
+  int n, width, height, tiles_x, item0;
+};
+constexpr int kMaxFitJobs = 16;
+struct FitJobsK {
+  FitJobK job[kMaxFitJobs];
+  int n_jobs, n_items;
+};
+
 struct KAdam {
   float lr_centre, lr_angle, lr_length, lr_width, lr_logits, lr_palette;
   float beta1, beta2, eps, bc1, bc2;
@@ -73,6 +89,7 @@ __global__ void k_palette_grad(const float* pal_terms, int n, int kpal, const fl
                                float* gpal);
 __global__ void k_loss_final(const float* part, int n_part, float inv_count, float* loss);
 __global__ void k_adam(float* prm, const float* grd, float* m, float* v, int n, int kpal, KAdam a);
+__global__ void k_fit_fused(FitJobsK jobs, int* cursor);
 __global__ void k_serve(const ServeDesc* descs, const uint2* items, int n_items, int* cursor);
 __global__ void k_fill_i32(int32_t* p, int n, int v);
 

@@ -68,6 +68,20 @@ WORKLOADS = {
 }
 
 
+# Batched fitting: 8 uneven jobs, two each of these (canvas side, strokes);
+# job j draws its initial program from seed 10 + 2j and its target program
+# from seed 11 + 2j, with the 2000-stroke distributions and 16 colours.
+BATCH_JOBS = ((512, 1000), (512, 1000), (1024, 2000), (1024, 2000), (1536, 3000), (1536, 3000),
+              (2048, 4000), (2048, 4000))
+
+
+def batch_job(j: int):
+    side, n = BATCH_JOBS[j]
+    w = Workload(f"batch{j}_{side}x{side}_n{n}", side, side, n, 16, DIST_LARGE, beta=2.0,
+                 tau_c=1.0, seed=10 + 2 * j, target_seed=11 + 2 * j)
+    return w
+
+
 def make_program(n: int, k: int, seed: int, dist: StrokeDist = DIST_SMALL,
                  beta: float = 1.0, dtype=np.float32) -> dict:
     """Draw one program of ``n`` capsule strokes over a ``k``-colour palette."""
