@@ -42,7 +42,7 @@ FLOPS_REPLAY = 291   # replay step: chart, Phi displacement, advance, VJP, wave 
 # HBM bytes per k_replay launch at the bench workload, from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
 # in the same runs; valid only for the kernel sources it was measured on.
-TRAFFIC = {"sha": "KERNEL_SHA", "k_replay_bytes": 355.6e6 + 262.5e6}
+TRAFFIC = {"sha": "fb2e2076638ad2e3", "k_replay_bytes": 389.2e6 + 262.5e6}
 
 
 def kernel_sha():
@@ -105,6 +105,36 @@ def ckpt_baseline(w, dprog, target, every=50, steps=2):
             "loss": float(loss), "impl": "PyTorch ops + torch.utils.checkpoint, FP32"}
 
 
+def ckpt_sweep(w, dprog, target, slots, intervals=(64, 128, 256, 512), steps=10):
+    """Fit-step time and workspace at several checkpoint intervals k (the
+    replay resets position and transmittance from a stored state every k
+    strokes): fewer checkpoints cost less memory and the same arithmetic."""
+    import torch
+    from paper_2609_08722_amd import api
+    out = []
+    for k in intervals:
+        opts = api.Opts(w.width, w.height, tau=w.tau, tau_c=w.tau_c, eps=w.eps, ckpt=k,
+                        side_slots=slots)
+        fit = api.FitState({f: v.clone() for f, v in dprog.items()}, opts,
+                           api.Adam(r_lo=0.002, r_hi=0.02, l_max=0.08))
+        for _ in range(3):
+            fit.step(target)
+        fit.tape_records()  # raises on overflow
+        stream = torch.cuda.current_stream()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(steps):
+            fit.step(target)
+        b.record(stream)
+        torch.cuda.synchronize()
+        out.append({"ckpt_interval": k, "ms_per_step": a.elapsed_time(b) / steps,
+                    "workspace_bytes": int(fit.nbytes)})
+        del fit
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_fit_benchmark(steps=3):
     """The 8-job uneven batch: fused multi-job step vs the same jobs stepped
     one after another with tbr_fit_step."""
@@ -160,10 +190,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ckpt-baseline", action="store_true",
                     help="skip the checkpointed-autograd PyTorch baseline")
+    ap.add_argument("--no-ckpt-sweep", action="store_true",
+                    help="skip the checkpoint-interval sweep of the fit step")
     ap.add_argument("--no-batched-fit", action="store_true",
                     help="skip the 8-job batched fit comparison")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="length of the Poisson serving replay (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0,
+                    help="Poisson arrival rate of the serving replay, requests/s")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this size (profiler calibration)")
     args = ap.parse_args()
@@ -297,16 +331,21 @@ def main():
         "paper_context": "fit step 0.52-0.55 s at 1024^2 x 2000 on one RTX PRO 4000 (FP32, fused "
                          "Triton): 3.8e9-4.0e9 pixel-stroke/s; different hardware, context only",
     }
+    del fit
+    torch.cuda.empty_cache()
+    if not args.no_ckpt_sweep:
+        out["ckpt_interval_sweep"] = ckpt_sweep(w, dprog, target, slots)
+        log(f"[bench] checkpoint sweep: {out['ckpt_interval_sweep']}")
     if not args.no_ckpt_baseline:
         out["ckpt_autograd_baseline"] = ckpt_baseline(w, dprog, target)
-    del fit
     torch.cuda.empty_cache()
     if not args.no_batched_fit:
         out["batched_fit"] = batched_fit_benchmark()
         log(f"[bench] batched fit: {out['batched_fit']}")
     if args.serve_seconds > 0:
         from paper_2609_08722_amd.serve_driver import serving_benchmark
-        out["serving"] = serving_benchmark(duration=args.serve_seconds, warmup=1.0)
+        out["serving"] = serving_benchmark(duration=args.serve_seconds, warmup=1.0,
+                                           rate=args.serve_rate)
         log(f"[bench] serving: {out['serving']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, prog, target_np)

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import require_gpu
+from gpu_util import group_errors, hard_parity, log, require_gpu
 from paper_2609_08722_amd import api, synth
 
 pytestmark = pytest.mark.gpu
@@ -85,3 +85,51 @@ def test_loss_decreases():
     losses = [fit.step(target).item() for _ in range(30)]
     assert losses[-1] < 0.8 * losses[0]
     assert fit.tape_records() >= 0
+
+
+def test_benchmark_workload_fit_step_matches_oracle_on_samples(orc):
+    """The benchmarked step at its full size (1024^2 x 2000, checkpoints
+    every 256 strokes, the same options and entry point): soft colours, hard
+    labels and the fit step's own gradient on 4096 sampled pixels (seed 3)
+    against the FP64 oracle. The target equals the step's own soft render
+    outside the samples, so the L2 seed vanishes there and the oracle can
+    take the gradient over the samples alone."""
+    require_gpu()
+    w = synth.WORKLOADS["fit1024x1024_n2000"]
+    W, H, P = w.width, w.height, w.pixels
+    prog = synth.workload_program(w)
+    dp = api.to_device(prog)
+    opts = api.Opts(W, H, tau=w.tau, tau_c=w.tau_c, eps=w.eps, ckpt=w.ckpt, side_slots=16)
+    out = api.render(dp, opts, "soft", tape=True)
+    R = out["rgb"].reshape(-1, 3)
+    hard = api.render(dp, api.Opts(W, H), "hard")
+    pix = synth.sample_pixels(P, 4096, 3)
+    ipix = torch.from_numpy(pix).cuda()
+    ref = orc.render(prog, W, H, tau=w.tau, tau_c=w.tau_c, eps=w.eps, pixels=pix)
+
+    ferr = np.abs(R[ipix].cpu().numpy() - ref["soft"])
+    exempt, bad = hard_parity(hard["owner"].reshape(-1)[ipix].cpu().numpy(),
+                              hard["label"].reshape(-1)[ipix].cpu().numpy(), ref)
+
+    # target: the step's render, replaced on the samples by another program's hard colours
+    tprog = synth.workload_program(w, seed=w.target_seed)
+    tref = orc.render(tprog, W, H, pixels=pix, soft=False)["hard"]
+    target = R.clone()
+    target[ipix] = torch.from_numpy(tref.astype(np.float32)).cuda()
+    opts.side_slots = out["tape"].max_records + 4
+    fit = api.FitState(dp, opts, api.Adam(lr_centre=0, lr_angle=0, lr_length=0, lr_width=0,
+                                           lr_logits=0, lr_palette=0))
+    loss = fit.step(target.reshape(H, W, 3)).item()
+    got = {k: v.cpu().numpy() for k, v in api.unpack(fit.grads, fit.n, fit.k).items()}
+    diff = R[ipix].cpu().numpy().astype(np.float64) - target[ipix].cpu().numpy()
+    seed = 2.0 * diff / (3.0 * P)
+    assert abs(loss - float(np.sum(diff ** 2)) / (3.0 * P)) <= 1e-5 * loss
+    r = orc.backward(prog, W, H, seed, tau=w.tau, tau_c=w.tau_c, eps=w.eps, pixels=pix)
+    refg = {f: r["geom"][q] for q, f in enumerate(api.GEOM)}
+    refg["logits"], refg["palette"] = r["logits"], r["palette"]
+    errs = {f: group_errors(got[f], refg[f])[0] for f in refg}
+    log(f"[{w.name}] soft max err {ferr.max():.2e}; hard exempt {exempt}, mismatches {bad}; "
+        f"grad rel errs {' '.join(f'{k}={v:.1e}' for k, v in errs.items())}")
+    assert ferr.max() <= 1e-4
+    assert bad == 0
+    assert max(errs.values()) <= 1e-3

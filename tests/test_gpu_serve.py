@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import log, require_gpu
+from gpu_util import hard_parity, log, require_gpu
 from paper_2609_08722_amd import api, serve_driver, synth
 
 pytestmark = pytest.mark.gpu
@@ -60,3 +60,54 @@ def test_short_poisson_replay_completes():
     log(f"[serve] {r}")
     assert r["requests"] == len(trace)
     assert r["p99_ms"] >= r["p50_ms"] > 0
+
+
+def test_full_size_requests_match_oracle_on_samples(orc):
+    """Requests at the serving mix's sizes (up to 2048^2 and 4000 strokes),
+    packed by a server configured as the serving benchmark configures it:
+    each result is bitwise the standalone render, and 4096 sampled pixels
+    per request match the FP64 oracle (soft colours within 1e-4; hard labels
+    and owners exactly, outside the 1e-5 boundary band)."""
+    require_gpu()
+    mix = synth.ServeMix()
+    lens = mix.program_lengths()
+    picks = [int(np.argmax(lens)), int(np.argmin(lens)), int(np.argsort(lens)[len(lens) // 2])]
+    progs = {j: synth.make_program(int(lens[j]), 8, mix.program_seed0 + j) for j in picks}
+    dps = {j: api.to_device(p) for j, p in progs.items()}
+    arena = sum(api.L.load().tbr_serve_program_bytes(len(p["cx"]), 8) for p in progs.values())
+    srv = api.Server(arena_bytes=arena + (96 << 20), max_slots=64, max_queue=1 << 16,
+                     max_tick_items=1 << 17, streams=3)
+    pids = {j: srv.register(dps[j]) for j in picks}
+    reqs = [(picks[0], 2048, "soft"), (picks[0], 2048, "hard"), (picks[1], 256, "soft"),
+            (picks[2], 1024, "hard"), (picks[2], 512, "soft"), (picks[1], 2048, "hard")]
+    outs = []
+    for j, W, mode in reqs:
+        rgb = torch.full((W, W, 3), -1.0, device="cuda")
+        label = torch.full((W, W), -7, dtype=torch.int32, device="cuda") if mode == "hard" else None
+        owner = torch.full((W, W), -7, dtype=torch.int32, device="cuda") if mode == "hard" else None
+        outs.append((rgb, label, owner))
+    tickets = [srv.submit(pids[j], mode, W, W, rgb=o[0], label=o[1], owner=o[2], tau_c=0.0)
+               for (j, W, mode), o in zip(reqs, outs)]
+    pending = set(tickets)
+    while pending:
+        for t in list(pending):
+            if srv.poll(t) is not None:
+                pending.discard(t)
+    torch.cuda.synchronize()
+    srv.close()
+    for q, ((j, W, mode), (rgb, label, owner)) in enumerate(zip(reqs, outs)):
+        alone = api.render(dps[j], api.Opts(W, W, tau_c=0.0), mode)
+        assert torch.equal(alone["rgb"], rgb), (j, W, mode)
+        pix = synth.sample_pixels(W * W, 4096, 300 + q)
+        ipix = torch.from_numpy(pix).cuda()
+        ref = orc.render(progs[j], W, W, tau_c=0.0, pixels=pix)
+        if mode == "soft":
+            err = float(np.abs(rgb.reshape(-1, 3)[ipix].cpu().numpy() - ref["soft"]).max())
+            log(f"[serve {W}^2 x {lens[j]} soft] max err {err:.2e}")
+            assert err <= 1e-4
+        else:
+            assert torch.equal(alone["label"], label) and torch.equal(alone["owner"], owner)
+            exempt, bad = hard_parity(owner.reshape(-1)[ipix].cpu().numpy(),
+                                      label.reshape(-1)[ipix].cpu().numpy(), ref)
+            log(f"[serve {W}^2 x {lens[j]} hard] exempt {exempt}, mismatches {bad}")
+            assert bad == 0
