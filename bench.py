@@ -118,8 +118,7 @@ def ckpt_sweep(w, dprog, target, slots, intervals=(64, 128, 256, 512), steps=10)
         fit = api.FitState({f: v.clone() for f, v in dprog.items()}, opts,
                            api.Adam(r_lo=0.002, r_hi=0.02, l_max=0.08))
         for _ in range(3):
-            fit.step(target)
-        fit.tape_records()  # raises on overflow
+            fit.step_checked(target, headroom=8)
         stream = torch.cuda.current_stream()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -244,12 +243,16 @@ def main():
     fit = api.FitState(dprog, opts, api.Adam(r_lo=0.002, r_hi=0.02, l_max=0.08))
     log(f"[bench] side table {slots} slots/pixel, fit workspace {fit.nbytes / 2**20:.1f} MiB")
 
-    torch.cuda.synchronize()
-    torch.cuda.reset_peak_memory_stats()
+    # warm-up steps grow the side table if the evolving program needs more
+    # records (an overflowed step skips its update and is repeated)
     for _ in range(args.warmup):
-        fit.step(target)
-    recs = fit.tape_records()  # raises on overflow
-    log(f"[bench] warmup done; side-table max records {recs}")
+        fit.step_checked(target, headroom=8)
+    slots = fit.opts.side_slots
+    recs = fit.tape_records()
+    log(f"[bench] warmup done; side-table max records {recs}, {slots} slots, "
+        f"workspace {fit.nbytes / 2**20:.1f} MiB")
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()  # peak over the timed steps
 
     # timed region: K whole steps, plus per-launch events around the replay
     # kernel and the soft trace kernel on the same stream
@@ -272,6 +275,10 @@ def main():
     stop.record(stream)
     torch.cuda.synchronize()
     lib.tbr_set_timing_events(None, None, None)
+    # every timed step must have kept its tape (an overflow would skip an update)
+    overflowed = fit._records()[0] == L.TBR_E_OVERFLOW
+    if overflowed:
+        log("[bench] WARNING: the side table overflowed during the timed steps")
     ms = start.elapsed_time(stop) / args.steps
     t_replay = [ev["replay"][s][0].elapsed_time(ev["replay"][s][1]) for s in range(0, args.steps, 2)]
     t_fwd = [ev["trace_soft"][s][0].elapsed_time(ev["trace_soft"][s][1])
@@ -327,6 +334,7 @@ def main():
         "hard_render_ms": hard_ms,
         "peak_hbm_bytes": int(peak),
         "side_table_max_records": int(recs),
+        "timed_steps_overflowed": bool(overflowed),
         "loss_after_steps": loss,
         "paper_context": "fit step 0.52-0.55 s at 1024^2 x 2000 on one RTX PRO 4000 (FP32, fused "
                          "Triton): 3.8e9-4.0e9 pixel-stroke/s; different hardware, context only",

@@ -161,7 +161,13 @@ size_t tbr_fit_workspace_bytes(const tbr_render_opts* opts, int32_t n_strokes,
  * grads: same layout, written (may be NULL: kept in the workspace).
  * adam_m, adam_v: Adam moments, same layout, updated in place.
  * target_rgb [H*W*3]; loss: device scalar, written (value before the update).
- * Half-width is clamped to [r_lo, r_hi], |length| to l_max, palette to [0,1]. */
+ * Half-width is clamped to [r_lo, r_hi], |length| to l_max, palette to [0,1].
+ * Side-table overflow (some pixel needed more than opts->side_slots records)
+ * is checked on the device before the update: the step then leaves params,
+ * adam_m and adam_v unchanged (grads and loss are written but describe an
+ * incomplete adjoint), and tbr_tape_records on this workspace reports
+ * TBR_E_OVERFLOW with the needed count. Growing side_slots and calling the
+ * step again repeats it exactly. */
 tbr_status tbr_fit_step(int32_t n_strokes, int32_t n_palette, float* params, float* grads,
                         float* adam_m, float* adam_v, const tbr_adam_opts* adam,
                         const tbr_render_opts* opts, const float* target_rgb, float* loss,
@@ -195,7 +201,8 @@ tbr_status tbr_fit_multi_step(const tbr_fit_job* jobs, int32_t n_jobs, void* wor
 
 /* Side-table high-water marks of the last multi step, per job
  * (max_records[n_jobs]). SYNCHRONISES the stream; TBR_E_OVERFLOW if any job
- * overflowed its side_slots. */
+ * overflowed its side_slots. A job that overflowed had its update skipped,
+ * as in tbr_fit_step; the other jobs were updated. */
 tbr_status tbr_fit_multi_records(const tbr_fit_job* jobs, int32_t n_jobs, const void* workspace,
                                  size_t workspace_bytes, int32_t* max_records, void* stream);
 

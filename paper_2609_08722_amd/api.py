@@ -246,19 +246,37 @@ class FitState:
                                  _ptr(self.loss), _ptr(self.ws), self.nbytes, _stream()))
         return self.loss
 
-    def tape_records(self) -> int:
-        """Max side-table records of the last step (synchronises); raises
-        TbrError(TBR_E_OVERFLOW) if the capacity was exceeded."""
+    def _records(self):
         lib = L.load()
         co = self.opts.c()
         mr = C.c_int32(0)
-        L.check(lib.tbr_tape_records(_ptr(self.ws), self.nbytes, C.byref(co), self.n,
-                                     C.byref(mr), _stream()))
-        return mr.value
+        st = lib.tbr_tape_records(_ptr(self.ws), self.nbytes, C.byref(co), self.n, C.byref(mr),
+                                  _stream())
+        return st, mr.value
+
+    def tape_records(self) -> int:
+        """Max side-table records of the last step (synchronises); raises
+        TbrError(TBR_E_OVERFLOW) if the capacity was exceeded."""
+        st, n = self._records()
+        L.check(st)
+        return n
 
     def grow_side_table(self, slots: int):
         self.opts = Opts(**{**self.opts.__dict__, "side_slots": int(slots)})
         self._alloc()
+
+    def step_checked(self, target: torch.Tensor, headroom: int = 4) -> torch.Tensor:
+        """One fit step that is repeated with a larger side table when the
+        table overflowed (the library then skipped the update, so the repeat
+        is exact). Synchronises the stream."""
+        while True:
+            loss = self.step(target)
+            st, need = self._records()
+            if st != L.TBR_E_OVERFLOW:
+                L.check(st)
+                return loss
+            self.step_index -= 1  # the update did not happen
+            self.grow_side_table(need + headroom)
 
 
 class MultiFit:

@@ -406,7 +406,8 @@ tbr_status tbr_fit_step(int32_t n_strokes, int32_t n_palette, float* params, flo
   if ((s = check_launch("loss_final"))) return s;
   if ((s = launch_backward(&prog, opts, rws, FL.r, seed, &pg, bws, FL.b, st))) return s;
   int total = (int)packed_len(N, K);
-  k_adam<<<(total + 255) / 256, 256, 0, st>>>(params, g, adam_m, adam_v, N, K, kadam(adam));
+  k_adam<<<(total + 255) / 256, 256, 0, st>>>(params, g, adam_m, adam_v, N, K, kadam(adam),
+                                              t.status, opts->side_slots);
   return check_launch("adam");
 }
 
@@ -502,8 +503,10 @@ tbr_status tbr_fit_multi_step(const tbr_fit_job* jobs, int32_t n_jobs, void* wor
     if ((s = check_launch("loss_final"))) return s;
     if ((s = launch_reduce(&progs[j], &J.opts, &pgrads[j], base + FL.base_b, FL.b, st))) return s;
     int total = (int)packed_len(J.n_strokes, J.n_palette);
+    const int32_t* recmax = reinterpret_cast<const int32_t*>(base + FL.base_r + FL.r.status);
     k_adam<<<(total + 255) / 256, 256, 0, st>>>(J.params, pgrads[j].cx, J.adam_m, J.adam_v,
-                                                J.n_strokes, J.n_palette, kadam(&J.adam));
+                                                J.n_strokes, J.n_palette, kadam(&J.adam), recmax,
+                                                J.opts.side_slots);
     if ((s = check_launch("adam"))) return s;
   }
   return TBR_OK;

@@ -1,6 +1,6 @@
 // tbr_device.hpp -- per-lane FP32 arithmetic of the capsule transport.
 //
-// One pixel per lane. Stroke constants arrive as a wave-uniform 64-byte
+// One pixel per lane. Stroke constants arrive as a wave-uniform 80-byte
 // record (scalar loads); everything else lives in VGPRs. All maps are the
 // closed forms of Sec. 4 of the paper (TBR, arxiv 2609.08722):
 //   distance sigma to the segment, Steiner area A_l(s) = 2 l s + pi s^2 and
@@ -30,12 +30,16 @@ constexpr float kLog2e = 1.44269504088896340736f;
 // alpha = e^z / (1 + e^z) <= 1 - 1e-7   <=>   e^z <= (1 - 1e-7) / 1e-7
 constexpr float kEzMax = 9999999.0f;
 
-// Per-stroke constants, prepared once per launch (64 bytes, 16 words).
+// Per-stroke constants, prepared once per launch (80 bytes, 20 words).
+// Wave-uniform values are precomputed here: the vector ALU would otherwise
+// spend a full instruction per wave on each of them.
 struct __align__(16) StrokeRec {
-  float mx, my;     // centre m
+  double mx, my;    // centre m, in FP64 like the trajectory state
   float ce, se;     // direction e = (cos phi, sin phi)
   float hl, ell;    // half-length l/2 and length l = |L|
+  float two_ell;    // 2 l
   float r, ar;      // half-width r and inserted area A_l(r)
+  float per_r;      // Steiner perimeter P_l(r) = 2 l + 2 pi r
   float inv_wd;     // 1 / max(tau r, tau_min)
   float floor_c;    // (eps r)^2
   float dfloor_dr;  // d (eps r)^2 / dr = 2 eps^2 r
@@ -43,7 +47,15 @@ struct __align__(16) StrokeRec {
   float cr, cg, cb; // colour c_i = softmax(z_i / tau_c) P (or P[argmax])
   int label;        // argmax_k z_ik (hard colour index)
 };
-static_assert(sizeof(StrokeRec) == 64, "stroke record must be 64 bytes");
+static_assert(sizeof(StrokeRec) == 80, "stroke record must be 80 bytes");
+
+// Wave votes over the active lanes: the ballot's lane mask is compared with
+// exec by scalar instructions, with no vector instruction beyond the compare
+// that produces the predicate.
+__device__ __forceinline__ bool wave_all(bool p) {
+  return __builtin_amdgcn_ballot_w64(p) == __builtin_amdgcn_read_exec();
+}
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -91,7 +103,7 @@ struct Chart {
 
 __device__ __forceinline__ Chart chart(double x, double y, const StrokeRec& g) {
   Chart c;
-  float dx = (float)(x - (double)g.mx), dy = (float)(y - (double)g.my);
+  float dx = (float)(x - g.mx), dy = (float)(y - g.my);
   c.s = fmaf(dx, g.ce, dy * g.se);
   c.h = fmaf(dy, g.ce, -(dx * g.se));
   c.sgs = c.s < 0.f ? -1.f : 1.f;
@@ -105,7 +117,7 @@ __device__ __forceinline__ Chart chart(double x, double y, const StrokeRec& g) {
   c.sn = c.E * inv_sig;
   c.cs = c.sig > 0.f ? c.H * inv_sig : 1.f;
   float t = fmaf(c.sig, c.th, fminf(c.S, g.hl));  // arclength from the flank midpoint
-  c.per = fmaf(kTwoPi, c.sig, g.ell + g.ell);      // P_l(sigma)
+  c.per = fmaf(kTwoPi, c.sig, g.two_ell);          // P_l(sigma)
   c.w = c.per > 0.f ? t * rcp(c.per) : 0.f;        // drop centre: w := 0
   return c;
 }
@@ -118,12 +130,12 @@ __device__ __forceinline__ float area_to_dist(float q, const StrokeRec& g) {
 
 // Backward numerator C = A(sigma') - A(r), factored (Eq. back).
 __device__ __forceinline__ float back_area(float sig, const StrokeRec& g) {
-  return (sig - g.r) * fmaf(kPi, sig + g.r, g.ell + g.ell);
+  return (sig - g.r) * fmaf(kPi, sig + g.r, g.two_ell);
 }
 
 // Forward numerator B = A(sigma) + A(r) (Eq. fwd).
 __device__ __forceinline__ float fwd_area(float sig, const StrokeRec& g) {
-  return fmaf(sig, fmaf(kPi, sig, g.ell + g.ell), g.ar);
+  return fmaf(sig, fmaf(kPi, sig, g.two_ell), g.ar);
 }
 
 // sin(d) and cos(d) - 1 for d in [-pi/2, pi/2] (odd / even polynomials).
@@ -142,6 +154,18 @@ __device__ __forceinline__ void sincosm1(float d, float& s, float& cm1) {
   pc = fmaf(pc, u, kCos[2]);
   pc = fmaf(pc, u, kCos[1]);
   cm1 = u * pc;  // kCos[0] == 1
+}
+
+// sin(d) and cos(d) - 1 for |d| < 1/16 by their Taylor series through d^5
+// and d^6: the first omitted terms are below |d|^7 / 5040 < 7.5e-13 and
+// d^8 / 40320 < 6e-15, far below FP32 resolution. A stroke turns a point's
+// cap angle by less than this almost always, so a wave whose lanes all do
+// takes these shorter polynomials.
+constexpr float kSmallTurn = 0.0625f;
+__device__ __forceinline__ void sincosm1_small(float d, float& s, float& cm1) {
+  float u = d * d;
+  s = d * fmaf(u, fmaf(u, 1.f / 120.f, -1.f / 6.f), 1.f);
+  cm1 = u * fmaf(u, fmaf(u, -1.f / 720.f, 1.f / 24.f), -0.5f);
 }
 
 // One application of the insertion map or its inverse to a charted point,
@@ -166,7 +190,7 @@ struct Move {
 
 __device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, bool backward) {
   Move m;
-  const float two_ell = g.ell + g.ell;
+  const float two_ell = g.two_ell;
   // psi: Eq. (back) with the implemented floor; Phi: Eq. (fwd)
   float cq = back_area(c.sig, g);
   m.floored = backward && cq < g.floor_c;
@@ -176,12 +200,18 @@ __device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, boo
   float dsig = num * rcp(fmaf(kPi, c.sig + m.sig_o, two_ell));
   float dt = kTwoPi * c.w * dsig;
   float t_o = c.w * fmaf(kTwoPi, m.sig_o, two_ell);
-  float th_o = fminf(fmaxf(t_o - g.hl, 0.f) * rcp(m.sig_o), kHalfPi);
+  const float inv_sig_o = rcp(m.sig_o);
+  float th_o = fminf(fmaxf(t_o - g.hl, 0.f) * inv_sig_o, kHalfPi);
   const bool cap_in = c.th > 0.f, cap_out = th_o > 0.f;
-  float dth_cc = dsig * g.ell * (kPi - 2.f * c.th) * rcp(c.per * m.sig_o);
+  // 1 / P_l(sig) is the chart's reciprocal (it also gives w)
+  float dth_cc = dsig * g.ell * (kPi - 2.f * c.th) * (rcp(c.per) * inv_sig_o);
   float dth = (cap_in && cap_out) ? dth_cc : th_o - c.th;
   float sd, cdm1;
-  sincosm1(dth, sd, cdm1);
+  if (wave_all(fabsf(dth) < kSmallTurn)) {
+    sincosm1_small(dth, sd, cdm1);
+  } else {
+    sincosm1(dth, sd, cdm1);
+  }
   float dsin = fmaf(c.sn, cdm1, c.cs * sd);
   float dcos = fmaf(c.cs, cdm1, -(c.sn * sd));
   m.sn_o = c.sn + dsin;
@@ -261,10 +291,12 @@ struct VjpOut {
   float gmx, gmy, gphi, gell, gr;        // stroke contributions
 };
 
+// kCover = false drops the coverage terms (a far stroke, alpha = 0 to FP32).
+template <bool kCover>
 __device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, float lx,
                                            float ly, float mu) {
   VjpOut o;
-  const float two_ell = g.ell + g.ell;
+  const float two_ell = g.two_ell;
   // out = m + sgs S' e + sgh H' n
   float ge = fmaf(lx, g.ce, ly * g.se);
   float gn = fmaf(ly, g.ce, -(lx * g.se));
@@ -289,7 +321,7 @@ __device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, f
   ellb = fmaf(-2.f * v.rho, cb, ellb);
   // C = A_l(sigma') - A_l(r), or the floor (eps r)^2
   float p1 = fmaf(kTwoPi, v.sig, two_ell);
-  float pr = fmaf(kTwoPi, g.r, two_ell);
+  const float pr = g.per_r;
   float sigb = v.floored ? 0.f : cb * p1;
   o.gr = v.floored ? cb * g.dfloor_dr : -(cb * pr);
   ellb = v.floored ? ellb : fmaf(2.f * (v.sig - g.r), cb, ellb);
@@ -305,10 +337,12 @@ __device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, f
   float eb = tb * v.cs;
   float hb = -(tb * v.sn);
   // coverage: z = (r - sigma') / wd
-  float zb = v.clamped ? 0.f : mu * v.alpha * v.q;
-  float zw = zb * g.inv_wd;
-  sigb -= zw;
-  o.gr = fmaf(zw, fmaf(-v.z, g.dwd_dr, 1.f), o.gr);
+  if constexpr (kCover) {
+    float zb = v.clamped ? 0.f : mu * v.alpha * v.q;
+    float zw = zb * g.inv_wd;
+    sigb -= zw;
+    o.gr = fmaf(zw, fmaf(-v.z, g.dwd_dr, 1.f), o.gr);
+  }
   // sigma' = sqrt(H^2 + E^2)
   hb = fmaf(sigb, v.cs, hb);
   eb = fmaf(sigb, v.sn, eb);

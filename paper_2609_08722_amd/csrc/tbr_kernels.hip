@@ -29,17 +29,19 @@ __global__ void __launch_bounds__(256)
   if (i == 0 && status) *status = 0;  // tape record high-water mark of this launch
   if (i >= p.n) return;
   StrokeRec g;
-  g.mx = p.cx[i];
-  g.my = p.cy[i];
+  g.mx = (double)p.cx[i];
+  g.my = (double)p.cy[i];
   float phi = p.angle[i];
   g.ce = cosf(phi);
   g.se = sinf(phi);
   float ell = fabsf(p.length[i]);
   g.ell = ell;
   g.hl = 0.5f * ell;
+  g.two_ell = ell + ell;
   float r = p.half_width[i];
   g.r = r;
   g.ar = r * fmaf(kPi, r, ell + ell);
+  g.per_r = fmaf(kTwoPi, r, ell + ell);
   float tr = o.tau * r;
   bool rel = tr > o.tau_min;
   float wd = rel ? tr : o.tau_min;
@@ -150,8 +152,10 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
     Chart c = chart(x, y, g);
     // Coverage and compositing, unless the stroke is far from every pixel
     // of the wave: then alpha < 7e-13, 1 - alpha rounds to 1 and T and C
-    // are unchanged to FP32 rounding.
-    if (!__all(((g.r - c.sig) * g.inv_wd < kFarZ) || !id.active)) {
+    // are unchanged to FP32 rounding. Lanes past a ragged canvas edge trace
+    // a point just outside the canvas and vote too: that can only keep the
+    // exact path.
+    if (!wave_all((g.r - c.sig) * g.inv_wd < kFarZ)) {
       Cover v = cover(c.sig, g);
       float t = trans_value(tm, te);
       float ta = t * v.alpha;
@@ -198,7 +202,7 @@ __device__ __forceinline__ void hard_pixel(const StrokeRec* __restrict__ recs, i
   own = -1;
   lab = 0;
   for (int i = n - 1; i >= 0; --i) {
-    if (__all(done)) break;
+    if (wave_all(done)) break;
     const StrokeRec g = load_rec(recs, i);
     if (!done) {
       Chart c = chart(x, y, g);
@@ -325,11 +329,12 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int n, int v) {
 }
 
 // ---------------------------------------------------------------------------
-// Cross-lane reduction of 8 per-lane values to wave totals.
+// Cross-lane reduction of 8 per-lane values to 16-lane row sums.
 // Three transpose stages halve the value set while exchanging with lane^1,
-// lane^2, lane^4 (DPP); lane^8 is a row rotation by 8; lane^16 and lane^32
-// use the gfx950 permlane swaps. Afterwards every lane holds the total of
-// value index bitrev3(lane & 7).
+// lane^2, lane^4 (DPP quad permutes and row shifts); lane^8 is a row
+// rotation by 8. Afterwards lanes l and l + 8 of each 16-lane row hold the
+// row's sum of value index bitrev3(l & 7). The four rows of a wave are added
+// later, in a fixed order, together with the block's other waves.
 // ---------------------------------------------------------------------------
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float v) {
@@ -341,7 +346,7 @@ constexpr int kRowShl4 = 0x104;
 constexpr int kRowShr4 = 0x114;
 constexpr int kRowRor8 = 0x128;
 
-__device__ __forceinline__ float wave_total8(const float (&v)[8], int lane) {
+__device__ __forceinline__ float row_sums8(const float (&v)[8], int lane) {
   const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
   float u[4];
 #pragma unroll
@@ -360,16 +365,11 @@ __device__ __forceinline__ float wave_total8(const float (&v)[8], int lane) {
   float r0 = w[0] + dpp_mov<kRowShl4>(w[0]);
   float r1 = w[1] + dpp_mov<kRowShr4>(w[1]);
   float t = b2 ? r1 : r0;
-  t += dpp_mov<kRowRor8>(t);
-  auto p16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(t), __float_as_uint(t), false, false);
-  t = __uint_as_float(p16[0]) + __uint_as_float(p16[1]);
-  auto p32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(t), __float_as_uint(t), false, false);
-  t = __uint_as_float(p32[0]) + __uint_as_float(p32[1]);
-  return t;
+  return t + dpp_mov<kRowRor8>(t);
 }
 
 // Same result when values 5..7 are zero (strokes far from the wave).
-__device__ __forceinline__ float wave_total5(const float (&v)[5], int lane) {
+__device__ __forceinline__ float row_sums5(const float (&v)[5], int lane) {
   const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
   float u[4];
   {
@@ -392,12 +392,7 @@ __device__ __forceinline__ float wave_total5(const float (&v)[5], int lane) {
   float r0 = w[0] + dpp_mov<kRowShl4>(w[0]);
   float r1 = w[1] + dpp_mov<kRowShr4>(w[1]);
   float t = b2 ? r1 : r0;
-  t += dpp_mov<kRowRor8>(t);
-  auto p16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(t), __float_as_uint(t), false, false);
-  t = __uint_as_float(p16[0]) + __uint_as_float(p16[1]);
-  auto p32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(t), __float_as_uint(t), false, false);
-  t = __uint_as_float(p32[0]) + __uint_as_float(p32[1]);
-  return t;
+  return t + dpp_mov<kRowRor8>(t);
 }
 
 __device__ __forceinline__ int value_index_of_lane(int lane) {
@@ -410,10 +405,13 @@ __device__ __forceinline__ int value_index_of_lane(int lane) {
 // table holds x_i (the floor bound there in the forward pass) or a
 // checkpoint resets the drift; then applies Eq. adjstep and accumulates
 // Eq. adjparam. Per stroke, 8 contributions (m_x, m_y, phi, l, r, c_rgb)
-// are reduced across the wave and then across the block's 4 waves in a
-// fixed order into the tile's partial row.
+// are reduced across each 16-lane row, and the block's 16 row sums are
+// then added in a fixed order into the tile's partial row.
 // ---------------------------------------------------------------------------
-constexpr int kChunk = 32;
+constexpr int kChunk = 16;
+// Block reduction buffer: [double buffer][wave * 4 + row][stroke of the
+// chunk, padded so the 4 rows of a wave write distinct banks][value].
+using ReduceLds = float[2][16][kChunk + 1][8];
 
 // The replay of one 16x16 tile by the whole block (all 256 threads must
 // call it). lcr, lcg, lcb: this lane's dL/dR; prow: the tile's partial row
@@ -422,8 +420,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, 
                                             const PixelId& id, int width, int height,
                                             const float* __restrict__ palette, float lcr,
                                             float lcg, float lcb, const KTape& tape,
-                                            float* __restrict__ prow,
-                                            float (&lds)[2][4][kChunk][8]) {
+                                            float* __restrict__ prow, ReduceLds& lds) {
   const float bgr = palette[0], bgg = palette[1], bgb = palette[2];
   const int P = width * height;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -451,13 +448,14 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, 
   {
     float t0 = trans_value(tm, te);
     float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, lcr * t0, lcg * t0, lcb * t0};
-    float tot = wave_total8(v, lane);
+    float tot = row_sums8(v, lane);
     __syncthreads();  // lds may still be read by a previous tile of this block
-    if (lane < 8) lds[0][wave][0][value_index_of_lane(lane)] = tot;
+    if (!(lane & 8)) lds[0][wave * 4 + (lane >> 4)][0][value_index_of_lane(lane)] = tot;
     __syncthreads();
     if (threadIdx.x < 8) {
-      float s = lds[0][0][0][threadIdx.x] + lds[0][1][0][threadIdx.x] +
-                lds[0][2][0][threadIdx.x] + lds[0][3][0][threadIdx.x];
+      float s = 0.f;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) s += lds[0][q][0][threadIdx.x];
       prow[(size_t)n * 8 + threadIdx.x] = s;
     }
     __syncthreads();
@@ -475,7 +473,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, 
       if (ck) next_ck = next_ck + k + 1 < n ? next_ck + k : 0x7fffffff;
       const bool pop = top_idx == i;
       float tot;
-      if (!ck && !__any(pop)) {
+      if (!ck && !wave_any(pop)) {
         // Common case: every lane regenerates x_i = Phi_i(x_{i-1}) (Eq. rpos).
         Chart ca = chart(x, y, g);
         Move mv = displace(ca, g, false);
@@ -498,17 +496,17 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, 
         vi.sn_o = ca.sn;
         vi.cs_o = ca.cs;
         advance(x, y, ca, mv, g);
-        if (__all(((g.r - vi.sig) * g.inv_wd < kFarZ) || !id.active)) {
+        if (wave_all((g.r - vi.sig) * g.inv_wd < kFarZ)) {
           // far stroke: alpha, mu dalpha and the colour terms vanish to FP32
           vi.z = 0.f;
           vi.alpha = 0.f;
           vi.q = 1.f;
           vi.clamped = true;
-          VjpOut vo = vjp_step(vi, g, lx, ly, 0.f);
+          VjpOut vo = vjp_step<false>(vi, g, lx, ly, 0.f);
           lx = vo.gx;
           ly = vo.gy;
           float v[5] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr};
-          tot = wave_total5(v, lane);
+          tot = row_sums5(v, lane);
         } else {
           Cover cv = cover(vi.sig, g);
           vi.z = cv.z;
@@ -522,11 +520,11 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, 
           float mu = t * (lc - lt);
           float ta = t * cv.alpha;
           lt = fmaf(cv.q, lt, cv.alpha * lc);
-          VjpOut vo = vjp_step(vi, g, lx, ly, mu);
+          VjpOut vo = vjp_step<true>(vi, g, lx, ly, mu);
           lx = vo.gx;
           ly = vo.gy;
           float v[8] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
-          tot = wave_total8(v, lane);
+          tot = row_sums8(v, lane);
         }
       } else {
         // Some lane takes x_i from the side table (the floor bound there in
@@ -606,19 +604,21 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, 
         float mu = t * (lc - lt);
         float ta = t * cv.alpha;
         lt = fmaf(cv.q, lt, cv.alpha * lc);
-        VjpOut vo = vjp_step(vi, g, lx, ly, mu);
+        VjpOut vo = vjp_step<true>(vi, g, lx, ly, mu);
         lx = vo.gx;
         ly = vo.gy;
         float v[8] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
-        tot = wave_total8(v, lane);
+        tot = row_sums8(v, lane);
       }
-      if (lane < 8) lds[buf][wave][j][value_index_of_lane(lane)] = tot;
+      if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
     }
     __syncthreads();
     {
       const int j = threadIdx.x >> 3, vv = threadIdx.x & 7;
       if (j < cn) {
-        float s = lds[buf][0][j][vv] + lds[buf][1][j][vv] + lds[buf][2][j][vv] + lds[buf][3][j][vv];
+        float s = 0.f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) s += lds[buf][q][j][vv];
         prow[(size_t)(c0 + j) * 8 + vv] = s;
       }
     }
@@ -630,7 +630,7 @@ __global__ void __launch_bounds__(256)
     k_replay(const StrokeRec* __restrict__ recs, int n, int width, int height,
              const float* __restrict__ palette, const float* __restrict__ grad_rgb, KTape tape,
              float* __restrict__ partial) {
-  __shared__ float lds[2][4][kChunk][8];
+  __shared__ ReduceLds lds;
   PixelId id = pixel_of_tile(blockIdx.x, blockIdx.y, width, height);
   const int tile = blockIdx.y * gridDim.x + blockIdx.x;
   float lcr = 0.f, lcg = 0.f, lcb = 0.f;
@@ -652,7 +652,7 @@ __global__ void __launch_bounds__(256)
 // tile, so the order in which blocks take tiles cannot change any sum.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_fit_fused(FitJobsK jobs, int* __restrict__ cursor) {
-  __shared__ float lds[2][4][kChunk][8];
+  __shared__ ReduceLds lds;
   __shared__ float red[256];
   __shared__ int item_s;
   for (;;) {
@@ -810,7 +810,12 @@ __global__ void k_loss_final(const float* __restrict__ part, int n_part, float i
 // [-l_max, l_max].
 __global__ void __launch_bounds__(256)
     k_adam(float* __restrict__ prm, const float* __restrict__ grd, float* __restrict__ m,
-           float* __restrict__ v, int n, int kpal, KAdam a) {
+           float* __restrict__ v, int n, int kpal, KAdam a, const int32_t* __restrict__ records,
+           int capacity) {
+  // A step whose side table overflowed has an incomplete adjoint: leave the
+  // parameters and moments as they were, so the step can be repeated with a
+  // larger table.
+  if (records && records[0] > capacity) return;
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   int total = 5 * n + n * kpal + 3 * kpal;
   if (e >= total) return;

@@ -88,7 +88,8 @@ __global__ void k_finalize(const double* groups, int n_groups, KProgram p, KOpts
 __global__ void k_palette_grad(const float* pal_terms, int n, int kpal, const float* gcol,
                                float* gpal);
 __global__ void k_loss_final(const float* part, int n_part, float inv_count, float* loss);
-__global__ void k_adam(float* prm, const float* grd, float* m, float* v, int n, int kpal, KAdam a);
+__global__ void k_adam(float* prm, const float* grd, float* m, float* v, int n, int kpal, KAdam a,
+                       const int32_t* records, int capacity);
 __global__ void k_fit_fused(FitJobsK jobs, int* cursor);
 __global__ void k_serve(const ServeDesc* descs, const uint2* items, int n_items, int* cursor);
 __global__ void k_fill_i32(int32_t* p, int n, int v);

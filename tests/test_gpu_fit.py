@@ -133,3 +133,33 @@ def test_benchmark_workload_fit_step_matches_oracle_on_samples(orc):
     assert ferr.max() <= 1e-4
     assert bad == 0
     assert max(errs.values()) <= 1e-3
+
+
+def test_side_table_overflow_skips_the_update_and_retry_is_exact():
+    """A step whose side table overflows leaves parameters and Adam moments
+    unchanged and reports the needed capacity; step_checked then repeats it
+    with a larger table, bitwise equal to a step that had room from the
+    start."""
+    prog, opts, target = setup(seed=35)
+    prog["half_width"] = prog["half_width"] * 4  # overlapping deposits: several records per pixel
+    dp = api.to_device(prog)
+    roomy = api.FitState(dp, api.Opts(**{**opts.__dict__, "side_slots": 32}))
+    roomy.step(target)
+    need = roomy.tape_records()
+    assert need >= 2
+    tight = api.FitState(dp, api.Opts(**{**opts.__dict__, "side_slots": 1}))
+    p0 = tight.params.clone()
+    tight.step(target)
+    with pytest.raises(api.L.TbrError):
+        tight.tape_records()
+    assert torch.equal(tight.params, p0)
+    assert not torch.any(tight.m) and not torch.any(tight.v)
+    tight.step_index -= 1
+    tight.grow_side_table(32)
+    tight.step(target)
+    assert tight.tape_records() == need
+    assert torch.equal(tight.params, roomy.params)
+    again = api.FitState(dp, api.Opts(**{**opts.__dict__, "side_slots": 1}))
+    again.step_checked(target)
+    assert again.opts.side_slots >= need
+    assert torch.equal(again.params, roomy.params) and torch.equal(again.m, roomy.m)
