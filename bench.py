@@ -42,7 +42,7 @@ FLOPS_REPLAY = 291   # replay step: chart, Phi displacement, advance, VJP, wave 
 # HBM bytes per k_replay launch at the bench workload, from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
 # in the same runs; valid only for the kernel sources it was measured on.
-TRAFFIC = {"sha": "fb2e2076638ad2e3", "k_replay_bytes": 389.2e6 + 262.5e6}
+TRAFFIC = {"sha": "7f5ff10d18f8919c", "k_replay_bytes": 389.8e6 + 262.5e6}
 
 
 def kernel_sha():

@@ -651,7 +651,10 @@ __global__ void __launch_bounds__(256)
 // tile (each lane reads back only its own tape). Partial rows are indexed by
 // tile, so the order in which blocks take tiles cannot change any sum.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_fit_fused(FitJobsK jobs, int* __restrict__ cursor) {
+// The forward and the replay share one register allocation here; asking for
+// 5 waves per SIMD (96 VGPRs, instead of 111 at 4 waves) spills only values
+// that live across a tile or a 16-stroke chunk, never inside a stroke loop.
+__global__ void __launch_bounds__(256, 5) k_fit_fused(FitJobsK jobs, int* __restrict__ cursor) {
   __shared__ ReduceLds lds;
   __shared__ float red[256];
   __shared__ int item_s;
