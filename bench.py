@@ -32,23 +32,23 @@ if ROOT not in sys.path:
 PEAK_FP32_FLOPS = 157.3e12
 # Algorithmic FP operations per pixel-stroke, counted from the formulas of
 # each phase (FMA = 2, every other FP32/FP64 operation incl. compare, select,
-# min/max, conversion and transcendental = 1); per-phase table in the design
-# notes. These are the counts of a stroke far from the pixel (coverage below
+# min/max, conversion and transcendental = 1). These are the counts of a
+# stroke far from the pixel (coverage below
 # 7e-13, no coverage or colour terms), the case of >99% of pixel-strokes here;
 # a near stroke needs 20 (forward) / 41 (replay) more. The path is ALU-bound:
 # HBM traffic is ~0.3 B per pixel-stroke.
 FLOPS_FWD = 163      # soft forward step with tape: chart, psi displacement, advance
 FLOPS_REPLAY = 291   # replay step: chart, Phi displacement, advance, VJP, wave reduction
-# HBM bytes per k_replay launch at the bench workload, from rocprofv3 --pmc
+# HBM bytes per k_fit_fused launch at the bench workload, from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
 # in the same runs; valid only for the kernel sources it was measured on.
-TRAFFIC = {"sha": "7f5ff10d18f8919c", "k_replay_bytes": 389.8e6 + 262.5e6}
+TRAFFIC = {"sha": "4eb44335fd650d16", "bytes": 367.6e6 + 589.9e6}
 
 
 def kernel_sha():
     import hashlib
     h = hashlib.sha256()
-    for f in ("tbr_kernels.hip", "tbr_device.hpp", "tbr_kernels.hpp"):
+    for f in ("tbr_kernels.hip", "tbr_device.hpp", "tbr_kernels.hpp", "tbr_api.hip"):
         with open(os.path.join(ROOT, "paper_2609_08722_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -254,23 +254,21 @@ def main():
     torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats()  # peak over the timed steps
 
-    # timed region: K whole steps, plus per-launch events around the replay
-    # kernel and the soft trace kernel on the same stream
+    # timed region: K whole steps, with HIP events recorded by the library
+    # around each step's fused forward + replay launch, on the same stream
     stream = torch.cuda.current_stream()
-    ev = {k: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)] for k in ("replay", "trace_soft")}
-    for pairs in ev.values():
-        for a, b in pairs:
-            a.record(stream)
-            b.record(stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    for a, b in ev:
+        a.record(stream)
+        b.record(stream)
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record(stream)
     for s in range(args.steps):
-        kname = "replay" if s % 2 == 0 else "trace_soft"
-        a, b = ev[kname][s]
-        L.check(lib.tbr_set_timing_events(kname.encode(), a.cuda_event, b.cuda_event))
+        a, b = ev[s]
+        L.check(lib.tbr_set_timing_events(b"fit_fused", a.cuda_event, b.cuda_event))
         fit.step(target)
     stop.record(stream)
     torch.cuda.synchronize()
@@ -280,30 +278,54 @@ def main():
     if overflowed:
         log("[bench] WARNING: the side table overflowed during the timed steps")
     ms = start.elapsed_time(stop) / args.steps
-    t_replay = [ev["replay"][s][0].elapsed_time(ev["replay"][s][1]) for s in range(0, args.steps, 2)]
-    t_fwd = [ev["trace_soft"][s][0].elapsed_time(ev["trace_soft"][s][1])
-             for s in range(1, args.steps, 2)]
-    ms_replay = float(np.mean(t_replay))
-    ms_fwd = float(np.mean(t_fwd)) if t_fwd else float("nan")
+    ms_fused = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     peak = torch.cuda.max_memory_allocated()
     loss = float(fit.loss.item())
     value = P * N / (ms * 1e-3)
-    log(f"[bench] {ms:.3f} ms/step; replay {ms_replay:.3f} ms, soft trace {ms_fwd:.3f} ms; "
+    log(f"[bench] {ms:.3f} ms/step; fused forward + replay {ms_fused:.3f} ms; "
         f"loss {loss:.6f}; peak {peak / 2**20:.0f} MiB")
 
-    achieved = FLOPS_REPLAY * P * N / (ms_replay * 1e-3)
-    traffic = TRAFFIC["k_replay_bytes"] if (TRAFFIC["sha"] == kernel_sha() and
-                                            w.name == "fit1024x1024_n2000") else None
-    roofline = {"bound": "alu", "kernel": "k_replay", "achieved": achieved / 1e12,
+    flops = FLOPS_FWD + FLOPS_REPLAY
+    achieved = flops * P * N / (ms_fused * 1e-3)
+    traffic = TRAFFIC["bytes"] if (TRAFFIC["sha"] == kernel_sha() and
+                                   w.name == "fit1024x1024_n2000") else None
+    roofline = {"bound": "alu", "kernel": "k_fit_fused", "achieved": achieved / 1e12,
                 "peak": PEAK_FP32_FLOPS / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_FLOPS, "traffic": traffic,
-                "flops_per_pixel_stroke": FLOPS_REPLAY, "launch_ms": ms_replay}
-    fwd_frac = FLOPS_FWD * P * N / (ms_fwd * 1e-3) / PEAK_FP32_FLOPS
+                "flops_per_pixel_stroke": flops, "launch_ms": ms_fused}
+
+    # the two halves as separate kernels (the render with tape and the
+    # replay adjoint behind tbr_render / tbr_render_backward), same program
+    cur = {k: v.contiguous() for k, v in fit.program().items()}
+    sep = {}
+    try:
+        R = api.render(cur, opts, "soft", tape=True)
+        seed = (R["rgb"] - target) * (2.0 / (3.0 * P))
+        api.render_backward(cur, R["tape"], seed)
+        for kname in ("trace_soft", "replay"):
+            t = []
+            for _ in range(5):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)  # torch creates the HIP event on its first record
+                b.record(stream)
+                L.check(lib.tbr_set_timing_events(kname.encode(), a.cuda_event, b.cuda_event))
+                if kname == "trace_soft":
+                    R = api.render(cur, opts, "soft", tape=True)
+                else:
+                    api.render_backward(cur, R["tape"], seed)
+                torch.cuda.synchronize()
+                t.append(a.elapsed_time(b))
+            lib.tbr_set_timing_events(None, None, None)
+            sep[kname] = float(np.mean(t))
+        del R, seed
+    except Exception as e:  # reported, never hides the main figure
+        lib.tbr_set_timing_events(None, None, None)
+        log(f"[bench] separate kernel timing failed: {e}")
+    log(f"[bench] separate kernels: {sep}")
 
     # hard render of the current program (what the paper scores)
     hard_ms = None
     try:
-        cur = {k: v.contiguous() for k, v in fit.program().items()}
         for _ in range(2):
             api.render(cur, opts, "hard")
         torch.cuda.synchronize()
@@ -325,12 +347,17 @@ def main():
         "config": {"workload": w.name, "width": w.width, "height": w.height, "n_strokes": N,
                    "n_palette": w.n_palette, "tau": w.tau, "tau_min": w.tau_min,
                    "tau_c": w.tau_c, "ckpt_interval": w.ckpt, "side_slots": slots,
-                   "step": "prep + soft trace with tape + L2 seed + replay adjoint + "
+                   "step": "prep + fused (soft trace with tape + L2 seed + replay adjoint) + "
                            "reduction + Adam"},
         "roofline": roofline,
-        "kernels_ms": {"k_replay": ms_replay, "k_trace_soft": ms_fwd},
-        "soft_trace_fp32_peak_frac": fwd_frac,
-        "step_fp32_peak_frac": (FLOPS_FWD + FLOPS_REPLAY) * P * N / (ms * 1e-3) / PEAK_FP32_FLOPS,
+        "kernels_ms": {"k_fit_fused": ms_fused,
+                       "separate": {"k_trace_soft": sep.get("trace_soft"),
+                                    "k_replay": sep.get("replay")}},
+        "separate_fp32_peak_frac": {
+            k: (f * P * N / (sep[n] * 1e-3) / PEAK_FP32_FLOPS if n in sep else None)
+            for k, f, n in (("k_trace_soft", FLOPS_FWD, "trace_soft"),
+                            ("k_replay", FLOPS_REPLAY, "replay"))},
+        "step_fp32_peak_frac": flops * P * N / (ms * 1e-3) / PEAK_FP32_FLOPS,
         "hard_render_ms": hard_ms,
         "peak_hbm_bytes": int(peak),
         "side_table_max_records": int(recs),

@@ -149,13 +149,16 @@ tbr_status tbr_render_backward(const tbr_program* prog, const tbr_render_opts* o
                                const tbr_program_grad* grad, void* workspace,
                                size_t workspace_bytes, void* stream);
 
-/* Workspace bytes for tbr_fit_step (tape + reduction + seeds + gradients). */
+/* Workspace bytes for tbr_fit_step (tape + reduction + gradients). */
 size_t tbr_fit_workspace_bytes(const tbr_render_opts* opts, int32_t n_strokes,
                                int32_t n_palette);
 
 /* One optimisation step of the inverse problem with the pixel L2 data term
  * L = mean((R - I*)^2) over the 3 H W values: soft render with tape, seed
- * dL/dR, replay adjoint, deterministic reduction, and an Adam update.
+ * dL/dR, replay adjoint, deterministic reduction, and an Adam update. The
+ * render, seed and replay of each 16x16 tile run back to back in one
+ * persistent launch (the kernel of tbr_fit_multi_step with one job); the
+ * results equal tbr_render + tbr_render_backward with that seed bitwise.
  * params: packed device vector [cx N | cy N | angle N | length N |
  *   half_width N | logits N*K | palette K*3], updated in place.
  * grads: same layout, written (may be NULL: kept in the workspace).

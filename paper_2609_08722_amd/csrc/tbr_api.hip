@@ -122,7 +122,7 @@ BackLayout back_layout(const tbr_render_opts* o, int n, int k) {
 struct FitLayout {
   RenderLayout r;
   BackLayout b;
-  size_t base_r, base_b, seed, loss_part, grads, total;
+  size_t base_r, base_b, loss_part, grads, cursor, total;
 };
 
 size_t packed_len(int n, int k) { return (size_t)5 * n + (size_t)n * k + (size_t)3 * k; }
@@ -136,12 +136,12 @@ FitLayout fit_layout(const tbr_render_opts* o, int n, int k) {
   off = align_up(off + L.r.total);
   L.base_b = off;
   off = align_up(off + L.b.total);
-  L.seed = off;
-  off = align_up(off + n_pixels(o) * 3 * sizeof(float));
   L.loss_part = off;
   off = align_up(off + n_tiles(o) * sizeof(float));
   L.grads = off;
   off = align_up(off + packed_len(n, k) * sizeof(float));
+  L.cursor = off;  // work cursor of the fused launch (single-job step)
+  off = align_up(off + sizeof(int));
   L.total = off;
   return L;
 }
@@ -222,6 +222,19 @@ tbr_status launch_reduce(const tbr_program* p, const tbr_render_opts* o, const t
   if ((s = check_launch("finalize"))) return s;
   k_palette_grad<<<p->n_palette * 3, 256, 0, st>>>(pal_terms, n, p->n_palette, gcol, g->palette);
   return check_launch("palette_grad");
+}
+
+// The fused fit kernel over the jobs' (job, tile) items; the cursor is
+// cleared by a fill kernel (no memset node if the caller captures a graph).
+tbr_status launch_fused(const FitJobsK& K, int* cursor, hipStream_t st) {
+  k_fill_i32<<<1, 64, 0, st>>>(cursor, 1, 0);
+  tbr_status s = check_launch("fill");
+  if (s) return s;
+  {
+    Timed tm("fit_fused", st);
+    k_fit_fused<<<std::min(K.n_items, 256 * 8), 256, 0, st>>>(K, cursor);
+  }
+  return check_launch("fit_fused");
 }
 
 tbr_status launch_backward(const tbr_program* p, const tbr_render_opts* o, const char* tape_ws,
@@ -392,19 +405,29 @@ tbr_status tbr_fit_step(int32_t n_strokes, int32_t n_palette, float* params, flo
   StrokeRec* recs = reinterpret_cast<StrokeRec*>(rws + FL.r.recs);
   KTape t = ktape(rws, FL.r, opts, true);
   if ((s = launch_prep(&prog, opts, recs, t.status, st))) return s;
-  float* seed = reinterpret_cast<float*>(ws + FL.seed);
   float* lpart = reinterpret_cast<float*>(ws + FL.loss_part);
-  dim3 grid(tiles_x(opts), tiles_y(opts));
-  {
-    Timed tm("trace_soft", st);
-    k_trace_soft<<<grid, 256, 0, st>>>(recs, N, opts->width, opts->height, prog.palette, nullptr,
-                                       t, KSeed{target_rgb, seed, lpart});
-  }
-  if ((s = check_launch("trace_soft"))) return s;
+  // soft forward with tape, L2 seed and replay adjoint of each tile in one
+  // persistent launch (one drain of the GPU per step instead of two)
+  FitJobsK KJ{};
+  KJ.n_jobs = 1;
+  FitJobK& D = KJ.job[0];
+  D.recs = recs;
+  D.palette = prog.palette;
+  D.target = target_rgb;
+  D.partial = reinterpret_cast<float*>(bws + FL.b.partial);
+  D.loss_part = lpart;
+  D.tape = t;
+  D.n = N;
+  D.width = opts->width;
+  D.height = opts->height;
+  D.tiles_x = tiles_x(opts);
+  D.item0 = 0;
+  KJ.n_items = (int)n_tiles(opts);
+  if ((s = launch_fused(KJ, reinterpret_cast<int*>(ws + FL.cursor), st))) return s;
   k_loss_final<<<1, 256, 0, st>>>(lpart, (int)n_tiles(opts), 1.0f / (3.0f * (float)n_pixels(opts)),
                                   loss);
   if ((s = check_launch("loss_final"))) return s;
-  if ((s = launch_backward(&prog, opts, rws, FL.r, seed, &pg, bws, FL.b, st))) return s;
+  if ((s = launch_reduce(&prog, opts, &pg, bws, FL.b, st))) return s;
   int total = (int)packed_len(N, K);
   k_adam<<<(total + 255) / 256, 256, 0, st>>>(params, g, adam_m, adam_v, N, K, kadam(adam),
                                               t.status, opts->side_slots);
@@ -485,14 +508,7 @@ tbr_status tbr_fit_multi_step(const tbr_fit_job* jobs, int32_t n_jobs, void* wor
     items += (int)n_tiles(&J.opts);
   }
   K.n_items = items;
-  int* cursor = reinterpret_cast<int*>(ws);
-  k_fill_i32<<<1, 64, 0, st>>>(cursor, 1, 0);
-  if ((s = check_launch("fill"))) return s;
-  {
-    Timed tm("fit_fused", st);
-    k_fit_fused<<<std::min(items, 256 * 8), 256, 0, st>>>(K, cursor);
-  }
-  if ((s = check_launch("fit_fused"))) return s;
+  if ((s = launch_fused(K, reinterpret_cast<int*>(ws), st))) return s;
   for (int j = 0; j < n_jobs; ++j) {
     const tbr_fit_job& J = jobs[j];
     const FitLayout& FL = layouts[j];
