@@ -185,9 +185,14 @@ struct Move {
   float sig_o;           // distance of the new point
   float dS, dH;          // folded displacement
   float th_o, sn_o, cs_o;  // cap angle of the new point and its sin / cos
+  float inv_per_o;       // 1 / P_l(sig_o) (kPer only)
   bool floored;          // psi only: the floor C >= (eps r)^2 bound
 };
 
+// kPer: also return 1 / P_l(sig_o). The root of Eq. (back) / Eq. (fwd)
+// satisfies sqrt(l^2 + pi q) = l + pi sig_o, so P_l(sig_o) =
+// 2 sqrt(l^2 + pi q): one reciprocal square root gives both.
+template <bool kPer = false>
 __device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, bool backward) {
   Move m;
   const float two_ell = g.two_ell;
@@ -196,7 +201,15 @@ __device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, boo
   m.floored = backward && cq < g.floor_c;
   float q = backward ? fmaxf(cq, g.floor_c) : fwd_area(c.sig, g);
   float num = backward ? (m.floored ? g.floor_c - c.sig * fmaf(kPi, c.sig, two_ell) : -g.ar) : g.ar;
-  m.sig_o = area_to_dist(q, g);
+  if constexpr (kPer) {
+    const float X = fmaf(g.ell, g.ell, kPi * q);
+    const float rs = __builtin_amdgcn_rsqf(X);
+    m.sig_o = q * rcp(g.ell + X * rs);
+    m.inv_per_o = 0.5f * rs;
+  } else {
+    m.sig_o = area_to_dist(q, g);
+    m.inv_per_o = 0.f;
+  }
   float dsig = num * rcp(fmaf(kPi, c.sig + m.sig_o, two_ell));
   float dt = kTwoPi * c.w * dsig;
   float t_o = c.w * fmaf(kTwoPi, m.sig_o, two_ell);
@@ -223,12 +236,17 @@ __device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, boo
   return m;
 }
 
+// Apply a displacement (a, b) along (e, n), unfolded, to the FP64 state.
+__device__ __forceinline__ void step_by(double& x, double& y, float a, float b,
+                                        const StrokeRec& g) {
+  x += (double)fmaf(a, g.ce, -(b * g.se));
+  y += (double)fmaf(a, g.se, b * g.ce);
+}
+
 // Apply a folded displacement to the FP64 state.
 __device__ __forceinline__ void advance(double& x, double& y, const Chart& c, const Move& m,
                                         const StrokeRec& g) {
-  float a = c.sgs * m.dS, b = c.sgh * m.dH;
-  x += (double)fmaf(a, g.ce, -(b * g.se));
-  y += (double)fmaf(a, g.se, b * g.ce);
+  step_by(x, y, c.sgs * m.dS, c.sgh * m.dH, g);
 }
 
 // Soft coverage alpha = sigmoid((r - sigma) / wd) with alpha <= 1 - 1e-7,
@@ -276,8 +294,9 @@ struct VjpIn {
   float sig;             // sigma' = distance of x_i
   float th, sn, cs;      // cap angle of x_i and its sin / cos (0, 0, 1 on the flank)
   float w;               // centred arclength fraction (common to both points)
+  float inv_p1;          // 1 / P_l(sigma') (0 at a drop centre)
   // output point x_{i-1}
-  float Sp, Hp;          // folded local coordinates
+  float so, ho;          // signed local coordinates
   float rho;             // distance of x_{i-1}
   float th_o, sn_o, cs_o;
   bool floored;          // the floor C >= (eps r)^2 bound at x_i
@@ -304,7 +323,7 @@ __device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, f
   float hbp = v.sgh * gn;  // adjoint of H'
   o.gmx = lx;
   o.gmy = ly;
-  o.gphi = fmaf(v.sgs * v.Sp, gn, -(v.sgh * v.Hp * ge));
+  o.gphi = fmaf(v.so, gn, -(v.ho * ge));
   // S' = min(t', l/2) + rho sin th', H' = rho cos th', th' = (t' - l/2) / rho
   float inv_rho = rcp(v.rho);
   float thb = v.rho * fmaf(sbp, v.cs_o, -(hbp * v.sn_o));
@@ -326,8 +345,7 @@ __device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, f
   o.gr = v.floored ? cb * g.dfloor_dr : -(cb * pr);
   ellb = v.floored ? ellb : fmaf(2.f * (v.sig - g.r), cb, ellb);
   // w = t / P_l(sigma')
-  float inv_p1 = p1 > 0.f ? rcp(p1) : 0.f;
-  float tb = wb * inv_p1;
+  float tb = wb * v.inv_p1;
   sigb = fmaf(-kTwoPi * v.w, tb, sigb);
   ellb = fmaf(-2.f * v.w, tb, ellb);
   // t = min(S, l/2) + sigma' th, th = atan2(E, H), E = S - l/2 (cap form,

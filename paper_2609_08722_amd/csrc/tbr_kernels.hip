@@ -476,26 +476,29 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, 
       if (!ck && !wave_any(pop)) {
         // Common case: every lane regenerates x_i = Phi_i(x_{i-1}) (Eq. rpos).
         Chart ca = chart(x, y, g);
-        Move mv = displace(ca, g, false);
-        float sb = ca.S + mv.dS, hb = ca.H + mv.dH;
+        Move mv = displace<true>(ca, g, false);
+        // unfolded displacement; the new point's signed coordinates are the
+        // chart's plus it (sgs (S + dS) = s + sgs dS, exactly)
+        const float da = ca.sgs * mv.dS, db = ca.sgh * mv.dH;
         VjpIn vi;
         vi.sgs = ca.sgs;
         vi.sgh = ca.sgh;
         vi.w = ca.w;
         vi.floored = false;
-        vi.s = ca.sgs * sb;
-        vi.h = ca.sgh * hb;
+        vi.s = ca.s + da;
+        vi.h = ca.h + db;
         vi.sig = mv.sig_o;
         vi.th = mv.th_o;
         vi.sn = mv.sn_o;
         vi.cs = mv.cs_o;
-        vi.Sp = ca.S;
-        vi.Hp = ca.H;
+        vi.inv_p1 = mv.inv_per_o;
+        vi.so = ca.s;
+        vi.ho = ca.h;
         vi.rho = ca.sig;
         vi.th_o = ca.th;
         vi.sn_o = ca.sn;
         vi.cs_o = ca.cs;
-        advance(x, y, ca, mv, g);
+        step_by(x, y, da, db, g);
         if (wave_all((g.r - vi.sig) * g.inv_wd < kFarZ)) {
           // far stroke: alpha, mu dalpha and the colour terms vanish to FP32
           vi.z = 0.f;
@@ -550,8 +553,9 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, 
         // for a loaded lane the chart is at x_i and psi_i gives the
         // (discarded) x_{i-1}, whose geometry the adjoint needs.
         Chart ca = chart(ax, ay, g);
-        Move mv = displace(ca, g, loaded);
-        float sb = ca.S + mv.dS, hb = ca.H + mv.dH;  // folded coordinates of the new point
+        Move mv = displace<true>(ca, g, loaded);
+        const float da = ca.sgs * mv.dS, db = ca.sgh * mv.dH;
+        const float sn_pt = ca.s + da, hn_pt = ca.h + db;  // signed coordinates of the new point
         VjpIn vi;
         vi.sgs = ca.sgs;
         vi.sgh = ca.sgh;
@@ -564,8 +568,9 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, 
           vi.th = ca.th;
           vi.sn = ca.sn;
           vi.cs = ca.cs;
-          vi.Sp = sb;
-          vi.Hp = hb;
+          vi.inv_p1 = ca.per > 0.f ? rcp(ca.per) : 0.f;
+          vi.so = sn_pt;
+          vi.ho = hn_pt;
           vi.rho = mv.sig_o;
           vi.th_o = mv.th_o;
           vi.sn_o = mv.sn_o;
@@ -573,19 +578,20 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, 
           x = ax;
           y = ay;
         } else {  // in = regenerated x_i, out = chart point x_{i-1}
-          vi.s = ca.sgs * sb;
-          vi.h = ca.sgh * hb;
+          vi.s = sn_pt;
+          vi.h = hn_pt;
           vi.sig = mv.sig_o;
           vi.th = mv.th_o;
           vi.sn = mv.sn_o;
           vi.cs = mv.cs_o;
-          vi.Sp = ca.S;
-          vi.Hp = ca.H;
+          vi.inv_p1 = mv.inv_per_o;
+          vi.so = ca.s;
+          vi.ho = ca.h;
           vi.rho = ca.sig;
           vi.th_o = ca.th;
           vi.sn_o = ca.sn;
           vi.cs_o = ca.cs;
-          advance(x, y, ca, mv, g);
+          step_by(x, y, da, db, g);
         }
         Cover cv = cover(vi.sig, g);
         vi.z = cv.z;
