@@ -220,3 +220,17 @@ def test_adjoint_degenerate_programs(orc):
                     groups=[f for f in GROUPS if f != "angle"])
         else:
             compare(g, r, 1e-3, name)
+
+
+def test_adjoint_argmax_colours(orc):
+    """tau_c = 0 (colours P[argmax z], the forward-only configurations):
+    geometry and palette gradients match the oracle, and the logits get no
+    gradient (the argmax is piecewise constant)."""
+    W, H = 64, 48
+    prog = synth.make_program(80, 8, 51, beta=1.0)
+    rng = np.random.default_rng(5)
+    seed = rng.normal(size=(W * H, 3)) * 1e-3
+    g, _ = gpu_grads(prog, W, H, seed, tau_c=0.0, ckpt=32)
+    r = orc_grads(orc, prog, W, H, seed, tau_c=0.0)
+    assert not np.any(g["logits"]) and not np.any(r["logits"])
+    compare(g, r, 1e-3, "argmax colours", groups=[f for f in GROUPS if f != "logits"])
