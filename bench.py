@@ -58,14 +58,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, prog, target_rgb, budget_s=12.0):
+def cpu_baseline(w, prog, target_rgb, budget_s=10.0):
     """The FP64 oracle (soft forward + adjoint) on a sample of pixels of the
-    same workload, on this host's cores."""
+    same workload, on this host's cores: a small probe, then one sample
+    sized to take about budget_s."""
     import oracle
     oracle.build(force=False)
     P = w.pixels
-    n = 256
-    while True:
+
+    def run(n):
         pix = np.sort(np.random.default_rng(3).choice(P, size=n, replace=False))
         t0 = time.perf_counter()
         r = oracle.render(prog, w.width, w.height, tau=w.tau, tau_min=w.tau_min, tau_c=w.tau_c,
@@ -73,10 +74,12 @@ def cpu_baseline(w, prog, target_rgb, budget_s=12.0):
         seed = 2.0 * (r["soft"] - target_rgb[pix]) / (3.0 * P)
         oracle.backward(prog, w.width, w.height, seed, tau=w.tau, tau_min=w.tau_min,
                         tau_c=w.tau_c, eps=w.eps, pixels=pix)
-        dt = time.perf_counter() - t0
-        if dt > budget_s / 4 or n >= P:
-            break
-        n = min(P, int(n * max(2.0, budget_s / max(dt, 1e-3) / 2)))
+        return time.perf_counter() - t0
+
+    n = 16384  # 64 of the oracle's 256-pixel blocks: every thread busy
+    dt = run(n)
+    n = min(P, max(n, int(n * budget_s / max(dt, 1e-3))))
+    dt = run(n)
     return {"value": n * w.n_strokes / dt, "unit": "pixel-stroke/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"FP64 soft forward + adjoint of {n} sampled pixels of the "
@@ -195,6 +198,8 @@ def main():
                     help="skip the 8-job batched fit comparison")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="length of the Poisson serving replay (0 = skip)")
+    ap.add_argument("--serve-warmup", type=float, default=1.0,
+                    help="leading seconds of the serving trace left out of the statistics")
     ap.add_argument("--serve-rate", type=float, default=200.0,
                     help="Poisson arrival rate of the serving replay, requests/s")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -379,8 +384,8 @@ def main():
         log(f"[bench] batched fit: {out['batched_fit']}")
     if args.serve_seconds > 0:
         from paper_2609_08722_amd.serve_driver import serving_benchmark
-        out["serving"] = serving_benchmark(duration=args.serve_seconds, warmup=1.0,
-                                           rate=args.serve_rate)
+        out["serving"] = serving_benchmark(duration=args.serve_seconds,
+                                           warmup=args.serve_warmup, rate=args.serve_rate)
         log(f"[bench] serving: {out['serving']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, prog, target_np)

@@ -8,6 +8,7 @@ spends waiting (for the server or for the plain loop) counts.
 
 from __future__ import annotations
 
+import sys
 import time
 
 import numpy as np
@@ -122,16 +123,22 @@ def run_plain(pool: Pool, trace, warmup: float, deadline: float):
             "pixel_strokes_per_s": ps / window if window > 0 else None}
 
 
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
 def serving_benchmark(duration=8.0, warmup=1.0, rate=200.0, plain=True):
     mix = synth.ServeMix(rate=rate)
     trace = mix.trace(duration)
     pool = Pool(mix)
     offered = sum(r.width * r.width * int(pool.lengths[r.program]) for r in trace) / duration
+    _log(f"[serve] {len(trace)} requests over {duration:g} s at {rate:g} req/s: server ...")
     out = {"workload": f"Poisson {rate:g} req/s, {duration:g} s ({len(trace)} requests, "
                        f"first {warmup:g} s warm-up), programs of 200-4000 strokes "
                        f"(log-uniform), hard/soft 50/50, 256^2-2048^2",
            "offered_pixel_strokes_per_s": offered,
            "server": run_server(pool, trace, warmup)}
     if plain:
+        _log("[serve] one request at a time ...")
         out["plain_one_at_a_time"] = run_plain(pool, trace, warmup, deadline=2.0 * duration)
     return out
