@@ -206,8 +206,8 @@ def main():
                     help="first run a plain device copy of this size (profiler calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the renderer's "
-              "multi-GPU sharding is a design note, not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the "
+              "renderer over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -223,6 +223,11 @@ tbr_status tbr_fit_multi_records(const tbr_fit_job* jobs, int32_t n_jobs, const 
  *      tbr_serve_request_bytes);
  *   3. packs all admitted requests into one persistent launch over
  *      (request, 16x16 tile) work items.
+ * Each stream owns a hipGraph built at create time: one copy of the tick's
+ * descriptors and work list from pinned host staging, a kernel that clears
+ * the work cursor, one stroke-preparation launch for all of the tick's
+ * requests and the persistent render launch. A tick updates the copy size
+ * and the launches' grids and arguments, then launches the graph.
  * Launches rotate over `streams` streams, so requests admitted while others
  * run overlap with them on the device. Every pixel is computed by the same
  * device code as tbr_render, so a request's result does not depend on what
@@ -267,8 +272,9 @@ typedef struct tbr_serve_stats {
 } tbr_serve_stats;
 
 /* Arena bytes of one resident program, of one admitted request, and of the
- * per-stream launch buffers (the arena must hold streams * tick bytes plus
- * the programs plus the in-flight requests). */
+ * per-stream launch buffers (descriptors, preparation descriptors, work list
+ * and cursor; the arena must hold streams * tick bytes plus the programs
+ * plus the in-flight requests). */
 size_t tbr_serve_program_bytes(int32_t n_strokes, int32_t n_palette);
 size_t tbr_serve_request_bytes(int32_t n_strokes);
 size_t tbr_serve_tick_bytes(const tbr_serve_opts* opts);

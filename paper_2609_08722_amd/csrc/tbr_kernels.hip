@@ -21,13 +21,9 @@
 namespace tbr {
 
 // ---------------------------------------------------------------------------
-// Stroke preparation: one thread per stroke.
+// Stroke preparation: the per-stroke constants of one record.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
-    k_stroke_prep(KProgram p, KOpts o, StrokeRec* __restrict__ out, int32_t* __restrict__ status) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0 && status) *status = 0;  // tape record high-water mark of this launch
-  if (i >= p.n) return;
+__device__ __forceinline__ StrokeRec prep_stroke(const KProgram& p, const KOpts& o, int i) {
   StrokeRec g;
   g.mx = (double)p.cx[i];
   g.my = (double)p.cy[i];
@@ -79,7 +75,29 @@ __global__ void __launch_bounds__(256)
   g.cr = cr;
   g.cg = cg;
   g.cb = cb;
-  out[i] = g;
+  return g;
+}
+
+// One thread per stroke of one program.
+__global__ void __launch_bounds__(256)
+    k_stroke_prep(KProgram p, KOpts o, StrokeRec* __restrict__ out, int32_t* __restrict__ status) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && status) *status = 0;  // tape record high-water mark of this launch
+  if (i >= p.n) return;
+  out[i] = prep_stroke(p, o, i);
+}
+
+// Every request of a serving tick in one launch: request j owns the blocks
+// [preps[j].block0, preps[j].block0 + ceil(n_j / 256)), one thread per
+// stroke (requests of empty programs own no block).
+__global__ void __launch_bounds__(256) k_serve_prep(const ServePrep* __restrict__ preps, int n_req) {
+  const int b = blockIdx.x;
+  int j = 0;
+  while (j + 1 < n_req && b >= preps[j + 1].block0) ++j;
+  j = __builtin_amdgcn_readfirstlane(j);
+  const ServePrep q = preps[j];
+  const int i = (b - q.block0) * 256 + (int)threadIdx.x;
+  if (b >= q.block0 && i < q.prog.n) q.out[i] = prep_stroke(q.prog, q.opts, i);
 }
 
 // Coverage below sigmoid(-28) = 7e-13 is skipped for a whole wave: 1 - alpha

@@ -52,6 +52,15 @@ struct ServeDesc {
   int pad[3];
 };
 
+// Stroke preparation of one request of a serving tick (read by k_serve_prep).
+struct ServePrep {
+  KProgram prog;
+  KOpts opts;
+  StrokeRec* out;  // the request's records in the arena
+  int block0;      // first block of this request in the tick's prep launch
+  int pad;
+};
+
 // One job of the fused multi-job fit (passed by value in the kernel arguments).
 struct FitJobK {
   const StrokeRec* recs;
@@ -92,6 +101,7 @@ __global__ void k_adam(float* prm, const float* grd, float* m, float* v, int n, 
                        const int32_t* records, int capacity);
 __global__ void k_fit_fused(FitJobsK jobs, int* cursor);
 __global__ void k_serve(const ServeDesc* descs, const uint2* items, int n_items, int* cursor);
+__global__ void k_serve_prep(const ServePrep* preps, int n_req);
 __global__ void k_fill_i32(int32_t* p, int n, int v);
 
 }  // namespace tbr

@@ -9,9 +9,13 @@
 //   2. admits queued requests in order while a slot is free and the arena
 //      can hold the request's prepared stroke records (its HBM footprint),
 //   3. packs every admitted-but-not-launched request into ONE persistent
-//      launch (k_serve) over a list of (request, 16x16 tile) work items,
-//      after launching the per-request stroke preparation on the same
-//      stream.
+//      launch (k_serve) over a list of (request, 16x16 tile) work items.
+//      A tick is a captured hipGraph built once per stream: one copy of
+//      the tick's descriptors and work list from pinned staging, a fill
+//      kernel that clears the work cursor, one stroke-preparation launch
+//      for all the tick's requests (k_serve_prep) and k_serve. Each tick
+//      only updates the copy size and the two launches' grids and
+//      arguments, then launches the graph.
 // Launches rotate over several streams, so requests admitted while others
 // are still on the GPU run concurrently with them. Each tile runs the same
 // per-pixel device functions as tbr_render, so results do not depend on the
@@ -127,13 +131,24 @@ struct Request {
   double t_submit = 0, t_admit = 0, t_start = 0, t_done = 0;
 };
 
+// Launch buffers of one tick, at `off` in the arena and mirrored in pinned
+// host staging: [ServeDesc x max_slots | ServePrep x max_slots |
+// uint2 items x max_tick_items], then (device only) the work cursor.
+struct TickLayout {
+  size_t desc, prep, items, cursor, staging, total;
+};
+
+TickLayout tick_layout(const tbr_serve_opts* o);
+
 struct Tick {
   bool busy = false;
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
-  size_t desc_off = 0, item_off = 0, cursor_off = 0;
-  ServeDesc* h_desc = nullptr;  // pinned staging
-  uint2* h_items = nullptr;
+  size_t off = 0;                // arena offset of the device launch buffers
+  char* h_stage = nullptr;       // pinned staging, TickLayout::staging bytes
+  hipGraph_t graph = nullptr;    // copy -> fill cursor -> prep -> serve
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t n_copy = nullptr, n_fill = nullptr, n_prep = nullptr, n_serve = nullptr;
   std::vector<uint64_t> tickets;
   double fake_done = 0;  // fake executor: modelled completion time
 };
@@ -169,6 +184,50 @@ size_t record_bytes(int n) { return align_up((size_t)(n > 0 ? n : 1) * sizeof(St
 int tiles_of(const tbr_request& r) {
   return ((r.width + 15) / 16) * ((r.height + 15) / 16);
 }
+
+TickLayout tick_layout(const tbr_serve_opts* o) {
+  TickLayout L{};
+  size_t off = 0;
+  L.desc = off;
+  off = align_up(off + (size_t)o->max_slots * sizeof(ServeDesc));
+  L.prep = off;
+  off = align_up(off + (size_t)o->max_slots * sizeof(ServePrep));
+  L.items = off;
+  off = align_up(off + (size_t)o->max_tick_items * sizeof(uint2));
+  L.staging = off;
+  L.cursor = off;
+  off = align_up(off + sizeof(int));
+  L.total = off;
+  return L;
+}
+
+// Kernel node parameters of the tick graph.
+hipKernelNodeParams prep_node(int blocks, void** args) {
+  hipKernelNodeParams kp{};
+  kp.func = reinterpret_cast<void*>(&k_serve_prep);
+  kp.gridDim = dim3(std::max(blocks, 1));
+  kp.blockDim = dim3(256);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  return kp;
+}
+
+hipKernelNodeParams serve_node(int n_items, void** args) {
+  hipKernelNodeParams kp{};
+  kp.func = reinterpret_cast<void*>(&k_serve);
+  // persistent grid: at most 8 blocks per CU, never more blocks than items
+  kp.gridDim = dim3(std::max(1, std::min(n_items, 256 * 8)));
+  kp.blockDim = dim3(256);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  return kp;
+}
+
+// Build the tick's graph once (with placeholder sizes that every launch
+// overwrites). Returns a HIP error code.
+hipError_t build_tick_graph(tbr_server* s, Tick& tk);
 
 // Called with the lock held.
 void retire(tbr_server* s) {
@@ -255,8 +314,12 @@ tbr_status launch(tbr_server* s) {
     tk->fake_done = t + cost;
     return TBR_OK;
   }
-  hipStream_t st = tk->stream;
-  int item = 0;
+  const TickLayout TL = tick_layout(&s->opts);
+  ServeDesc* h_desc = reinterpret_cast<ServeDesc*>(tk->h_stage + TL.desc);
+  ServePrep* h_prep = reinterpret_cast<ServePrep*>(tk->h_stage + TL.prep);
+  uint2* h_items = reinterpret_cast<uint2*>(tk->h_stage + TL.items);
+  char* dbase = s->base + tk->off;
+  int item = 0, blocks = 0;
   for (size_t j = 0; j < take.size(); ++j) {
     Request& r = s->requests[take[j]];
     const Program& pg = s->programs[r.req.program_id];
@@ -268,8 +331,13 @@ tbr_status launch(tbr_server* s) {
     float tau_min = r.req.tau_min > 0.f ? r.req.tau_min : (float)(0.7 / (double)r.req.width);
     KOpts ko{r.req.tau, tau_min, r.req.tau_c, r.req.eps_floor};
     StrokeRec* recs = reinterpret_cast<StrokeRec*>(s->base + r.rec_off);
-    int nb = std::max(1, (n + 255) / 256);
-    k_stroke_prep<<<nb, 256, 0, st>>>(kp, ko, recs, nullptr);
+    ServePrep q{};
+    q.prog = kp;
+    q.opts = ko;
+    q.out = recs;
+    q.block0 = blocks;
+    h_prep[j] = q;
+    blocks += (n + 255) / 256;
     ServeDesc d{};
     d.recs = recs;
     d.palette = kp.palette;
@@ -281,28 +349,63 @@ tbr_status launch(tbr_server* s) {
     d.height = r.req.height;
     d.tiles_x = (r.req.width + 15) / 16;
     d.soft = r.req.mode == TBR_SOFT ? 1 : 0;
-    tk->h_desc[j] = d;
-    for (int q = 0; q < r.tiles; ++q) tk->h_items[item++] = make_uint2((unsigned)j, (unsigned)q);
+    h_desc[j] = d;
+    for (int q2 = 0; q2 < r.tiles; ++q2) h_items[item++] = make_uint2((unsigned)j, (unsigned)q2);
     r.state = kRunning;
     r.t_start = t;
   }
-  ServeDesc* d_desc = reinterpret_cast<ServeDesc*>(s->base + tk->desc_off);
-  uint2* d_items = reinterpret_cast<uint2*>(s->base + tk->item_off);
-  int* d_cursor = reinterpret_cast<int*>(s->base + tk->cursor_off);
-  hipError_t e = hipMemcpyAsync(d_desc, tk->h_desc, take.size() * sizeof(ServeDesc),
-                                hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(d_items, tk->h_items, (size_t)n_items * sizeof(uint2),
-                       hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return sfail(TBR_E_DEVICE, "serve copy: %s", hipGetErrorString(e));
-  k_fill_i32<<<1, 64, 0, st>>>(d_cursor, 1, 0);
-  // persistent grid: at most 8 blocks per CU, never more blocks than items
-  int grid = std::min(n_items, 256 * 8);
-  k_serve<<<grid, 256, 0, st>>>(d_desc, d_items, n_items, d_cursor);
-  e = hipGetLastError();
-  if (e == hipSuccess) e = hipEventRecord(tk->done, st);
+  // update the tick graph: copy size, prep grid, serve grid and arguments
+  const ServePrep* d_prep = reinterpret_cast<const ServePrep*>(dbase + TL.prep);
+  const ServeDesc* d_desc = reinterpret_cast<const ServeDesc*>(dbase + TL.desc);
+  const uint2* d_items = reinterpret_cast<const uint2*>(dbase + TL.items);
+  int* d_cursor = reinterpret_cast<int*>(dbase + TL.cursor);
+  int n_req = (int)take.size();
+  void* prep_args[2] = {&d_prep, &n_req};
+  void* serve_args[4] = {&d_desc, &d_items, &n_items, &d_cursor};
+  hipKernelNodeParams pp = prep_node(blocks, prep_args);
+  hipKernelNodeParams sp = serve_node(n_items, serve_args);
+  const size_t bytes = TL.items + (size_t)n_items * sizeof(uint2);
+  hipError_t e = hipGraphExecMemcpyNodeSetParams1D(tk->exec, tk->n_copy, dbase, tk->h_stage,
+                                                  bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(tk->exec, tk->n_prep, &pp);
+  if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(tk->exec, tk->n_serve, &sp);
+  if (e == hipSuccess) e = hipGraphLaunch(tk->exec, tk->stream);
+  if (e == hipSuccess) e = hipEventRecord(tk->done, tk->stream);
   if (e != hipSuccess) return sfail(TBR_E_DEVICE, "serve launch: %s", hipGetErrorString(e));
   return TBR_OK;
+}
+
+hipError_t build_tick_graph(tbr_server* s, Tick& tk) {
+  const TickLayout TL = tick_layout(&s->opts);
+  char* dbase = s->base + tk.off;
+  const ServePrep* d_prep = reinterpret_cast<const ServePrep*>(dbase + TL.prep);
+  const ServeDesc* d_desc = reinterpret_cast<const ServeDesc*>(dbase + TL.desc);
+  const uint2* d_items = reinterpret_cast<const uint2*>(dbase + TL.items);
+  int* d_cursor = reinterpret_cast<int*>(dbase + TL.cursor);
+  int one = 1, zero = 0, n_req = 1, n_items = 0;
+  hipError_t e = hipGraphCreate(&tk.graph, 0);
+  if (e != hipSuccess) return e;
+  e = hipGraphAddMemcpyNode1D(&tk.n_copy, tk.graph, nullptr, 0, dbase, tk.h_stage, TL.staging,
+                              hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  // the cursor is cleared by a fill kernel, not a memset node
+  void* fill_args[3] = {&d_cursor, &one, &zero};
+  hipKernelNodeParams fp{};
+  fp.func = reinterpret_cast<void*>(&k_fill_i32);
+  fp.gridDim = dim3(1);
+  fp.blockDim = dim3(64);
+  fp.kernelParams = fill_args;
+  e = hipGraphAddKernelNode(&tk.n_fill, tk.graph, &tk.n_copy, 1, &fp);
+  if (e != hipSuccess) return e;
+  void* prep_args[2] = {&d_prep, &n_req};
+  hipKernelNodeParams pp = prep_node(1, prep_args);
+  e = hipGraphAddKernelNode(&tk.n_prep, tk.graph, &tk.n_fill, 1, &pp);
+  if (e != hipSuccess) return e;
+  void* serve_args[4] = {&d_desc, &d_items, &n_items, &d_cursor};
+  hipKernelNodeParams sp = serve_node(n_items, serve_args);
+  e = hipGraphAddKernelNode(&tk.n_serve, tk.graph, &tk.n_prep, 1, &sp);
+  if (e != hipSuccess) return e;
+  return hipGraphInstantiate(&tk.exec, tk.graph, nullptr, nullptr, 0);
 }
 
 void worker_loop(tbr_server* s) {
@@ -339,8 +442,7 @@ extern "C" {
 
 size_t tbr_serve_tick_bytes(const tbr_serve_opts* opts) {
   if (!opts || opts->max_slots < 1 || opts->max_tick_items < 1) return 0;
-  return align_up((size_t)opts->max_slots * sizeof(ServeDesc)) +
-         align_up((size_t)opts->max_tick_items * sizeof(uint2)) + kAlign;
+  return tick_layout(opts).total;
 }
 
 size_t tbr_serve_program_bytes(int32_t n_strokes, int32_t n_palette) {
@@ -362,25 +464,21 @@ tbr_status tbr_serve_create(const tbr_serve_opts* opts, tbr_server** out) {
   s->base = static_cast<char*>(opts->arena);
   s->arena.init(opts->arena_bytes);
   s->ticks.resize(opts->streams);
-  const size_t tick_bytes = tbr_serve_tick_bytes(opts);
+  const TickLayout TL = tick_layout(opts);
   for (auto& tk : s->ticks) {
     size_t off;
-    if (!s->arena.alloc(tick_bytes, &off)) {
+    if (!s->arena.alloc(TL.total, &off)) {
       tbr_serve_destroy(s);
       return sfail(TBR_E_NOMEM, "arena too small for %d launch buffers", opts->streams);
     }
-    tk.desc_off = off;
-    tk.item_off = off + align_up((size_t)opts->max_slots * sizeof(ServeDesc));
-    tk.cursor_off = tk.item_off + align_up((size_t)opts->max_tick_items * sizeof(uint2));
+    tk.off = off;
     if (!opts->fake_device) {
       hipError_t e = hipStreamCreateWithFlags(&tk.stream, hipStreamNonBlocking);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&tk.done, hipEventDisableTiming);
       if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&tk.h_desc),
-                          (size_t)opts->max_slots * sizeof(ServeDesc), hipHostMallocDefault);
-      if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&tk.h_items),
-                          (size_t)opts->max_tick_items * sizeof(uint2), hipHostMallocDefault);
+        e = hipHostMalloc(reinterpret_cast<void**>(&tk.h_stage), TL.staging,
+                          hipHostMallocDefault);
+      if (e == hipSuccess) e = build_tick_graph(s, tk);
       if (e != hipSuccess) {
         tbr_serve_destroy(s);
         return sfail(TBR_E_DEVICE, "serve create: %s", hipGetErrorString(e));
@@ -531,10 +629,11 @@ void tbr_serve_destroy(tbr_server* s) {
   if (s->worker.joinable()) s->worker.join();
   for (auto& tk : s->ticks) {
     if (tk.stream) (void)hipStreamSynchronize(tk.stream);
+    if (tk.exec) (void)hipGraphExecDestroy(tk.exec);
+    if (tk.graph) (void)hipGraphDestroy(tk.graph);
     if (tk.done) (void)hipEventDestroy(tk.done);
     if (tk.stream) (void)hipStreamDestroy(tk.stream);
-    if (tk.h_desc) (void)hipHostFree(tk.h_desc);
-    if (tk.h_items) (void)hipHostFree(tk.h_items);
+    if (tk.h_stage) (void)hipHostFree(tk.h_stage);
   }
   delete s;
 }

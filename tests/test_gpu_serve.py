@@ -111,3 +111,39 @@ def test_full_size_requests_match_oracle_on_samples(orc):
                                       label.reshape(-1)[ipix].cpu().numpy(), ref)
             log(f"[serve {W}^2 x {lens[j]} hard] exempt {exempt}, mismatches {bad}")
             assert bad == 0
+
+
+def test_tick_graph_replays_match_eager_renders():
+    """One stream, so every tick replays the same captured graph with new
+    parameters: six rounds of requests, each waited for, with eager renders
+    and synchronisations in between; every result must equal the eager
+    render bitwise."""
+    require_gpu()
+    rng = np.random.default_rng(11)
+    progs = [synth.make_program(int(n), 8, 700 + j) for j, n in enumerate((120, 640, 1500))]
+    dps = [api.to_device(p) for p in progs]
+    srv = api.Server(arena_bytes=64 << 20, max_slots=4, streams=1)
+    pids = [srv.register(p) for p in dps]
+    for rnd in range(6):
+        reqs = []
+        for q in range(int(rng.integers(1, 4))):
+            j = int(rng.integers(0, 3))
+            W = int(rng.choice([32, 80, 128, 200]))
+            mode = "soft" if rng.random() < 0.5 else "hard"
+            rgb = torch.full((W, W, 3), -1.0, device="cuda")
+            reqs.append((j, W, mode, rgb, srv.submit(pids[j], mode, W, W, rgb=rgb, tau_c=0.0)))
+        pending = {t for *_, t in reqs}
+        while pending:
+            for t in list(pending):
+                if srv.poll(t) is not None:
+                    pending.discard(t)
+        # eager work between replays
+        api.render(dps[rnd % 3], api.Opts(48, 48, tau_c=0.0), "soft")
+        torch.cuda.synchronize()
+        for j, W, mode, rgb, _ in reqs:
+            alone = api.render(dps[j], api.Opts(W, W, tau_c=0.0), mode)
+            assert torch.equal(alone["rgb"], rgb), (rnd, j, W, mode)
+    stats = srv.stats()
+    srv.close()
+    log(f"[serve] graph replays: {stats['launches']} ticks on one stream")
+    assert stats["launches"] >= 6
