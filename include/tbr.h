@@ -32,8 +32,9 @@
  *     The background is P[0].
  *   - Scalar arguments are validated on the host: a violation returns
  *     TBR_E_INVALID without launching anything, and tbr_last_error() says
- *     why. Device array contents are not inspected (NaN propagates; r <= 0
- *     is undefined). Launch failures return TBR_E_DEVICE. No call aborts.
+ *     why. Device array contents are not inspected: NaN values or r <= 0
+ *     give unspecified results (the device code is compiled assuming no
+ *     NaN). Launch failures return TBR_E_DEVICE. No call aborts.
  *   - Calls are re-entrant given distinct workspaces.
  */
 #ifndef TBR_H_
