@@ -42,7 +42,7 @@ FLOPS_REPLAY = 291   # replay step: chart, Phi displacement, advance, VJP, wave 
 # HBM bytes per k_fit_fused launch at the bench workload, from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
 # in the same runs; valid only for the kernel sources it was measured on.
-TRAFFIC = {"sha": "ccfc283dcbb11f55", "bytes": 353.4e6 + 582.1e6}
+TRAFFIC = {"sha": "dc483b2c60b169e4", "bytes": 355.3e6 + 581.8e6}
 
 
 def kernel_sha():
