@@ -69,3 +69,28 @@ def test_batch_mix_kernels_match_oracle_on_samples(orc):
             f"grad rel errs {' '.join(f'{k}={v:.1e}' for k, v in errs.items())}")
         assert ferr <= 1e-4
         assert max(errs.values()) <= 1e-3
+
+
+def test_overflowing_job_skips_only_its_own_update():
+    """A job whose side table overflows leaves its parameters and moments
+    unchanged; the other jobs of the same multi step are updated exactly as
+    their single-job steps would be."""
+    require_gpu()
+    jobs = small_jobs()[:2]
+    big = {**jobs[0][0], "half_width": jobs[0][0]["half_width"] * 4}  # several records per pixel
+    tight = api.FitState(api.to_device(big), api.Opts(**{**jobs[0][1].__dict__, "side_slots": 1}))
+    other = api.FitState(api.to_device(jobs[1][0]), jobs[1][1])
+    single = api.FitState(api.to_device(jobs[1][0]), jobs[1][1])
+    p0, m0 = tight.params.clone(), tight.m.clone()
+    multi = api.MultiFit([tight, other])
+    multi.step([jobs[0][2], jobs[1][2]])
+    single.step(jobs[1][2])
+    torch.cuda.synchronize()
+    lib = api.L.load()
+    out = (api.C.c_int32 * 2)()
+    st = lib.tbr_fit_multi_records(multi._jobs(), 2, api._ptr(multi.ws), multi.nbytes, out,
+                                   api._stream())
+    assert st == api.L.TBR_E_OVERFLOW
+    assert out[0] > 1 and out[1] <= jobs[1][1].side_slots
+    assert torch.equal(tight.params, p0) and torch.equal(tight.m, m0)
+    assert torch.equal(other.params, single.params)
