@@ -7,8 +7,9 @@ reduction, colour/palette chain rule and the Adam update (tbr_fit_step).
 The metric is pixel-stroke evaluations per second, P * N / step time.
 
 Also reported: the hard render of the fitted program, the checkpointed-
-autograd PyTorch baseline on the same inputs, a Poisson serving replay
-(continuous batching vs one request at a time) and the FP64 CPU oracle.
+autograd PyTorch baseline on the same inputs, the whole 240-step fitting
+loop, a Poisson serving replay (continuous batching vs one request at a
+time) and the FP64 CPU oracle.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 Prints ONE JSON line. Only one GPU is used; --gpus above 1 exits.
@@ -42,7 +43,7 @@ FLOPS_REPLAY = 291   # replay step: chart, Phi displacement, advance, VJP, wave 
 # HBM bytes per k_fit_fused launch at the bench workload, from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
 # in the same runs; valid only for the kernel sources it was measured on.
-TRAFFIC = {"sha": "dc483b2c60b169e4", "bytes": 355.3e6 + 581.8e6}
+TRAFFIC = {"sha": "0766b694f7d3b895", "bytes": 361.4e6 + 588.0e6}
 
 
 def kernel_sha():
@@ -183,6 +184,67 @@ def batched_fit_benchmark(steps=3):
             "side_table_max_records": recs, "fused_equals_sequential": bool(same)}
 
 
+def fit_loop_benchmark():
+    """The whole fitting loop of Table hyper at 1024^2 x 2000 with an 8-colour
+    palette: 240 steps of window map, fit step, regularisers and windowed
+    Adam, tau and the colour temperature annealed, cosine step decay. A first
+    pass sizes the side table (an overflowing step grows it and is
+    repeated); the timed pass reruns the loop from the same start with that
+    table and no host synchronisation, and must end on bitwise the same
+    parameters (the steps are deterministic, so no step of it overflowed)."""
+    import torch
+    from paper_2609_08722_amd import api, synth
+    from paper_2609_08722_amd import fitloop as fl
+    c = synth.LOOP_FIT
+    W, H, n, k, T = c["width"], c["height"], c["n"], c["k"], c["steps"]
+    win, sched = fl.Window(), fl.Schedule(total_steps=T)
+    th_t = torch.tensor(synth.loop_theta(n, k, c["target_seed"]), device="cuda")
+    target = api.render(api.unpack(fl.window_map(th_t, n, k, win), n, k), api.Opts(W, H),
+                        "hard")["rgb"]
+    th0 = torch.tensor(synth.loop_theta(n, k, c["seed"]), device="cuda")
+
+    def hard_mse(loop):
+        rgb = api.render(loop.program(), api.Opts(W, H), "hard")["rgb"]
+        return torch.mean((rgb.double() - target.double()) ** 2).item()
+
+    first = fl.FitLoop(th0, n, k, W, H, window=win, schedule=sched, side_slots=8)
+    mse0 = hard_mse(first)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = [first.step_checked(target, headroom=4).item() for _ in range(T)]
+    t_checked = time.perf_counter() - t0
+    slots = first.opts.side_slots
+    log(f"[bench] fit loop sizing pass: {t_checked:.2f} s, side table {slots} slots")
+
+    loop = fl.FitLoop(th0, n, k, W, H, window=win, schedule=sched, side_slots=slots)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(T):
+        loop.step(target)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = e0.elapsed_time(e1) * 1e-3
+    same = torch.equal(loop.theta, first.theta)
+    mse1 = hard_mse(loop)
+    exported = api.render(fl.export(loop.program()), api.Opts(W, H), "hard")["rgb"]
+    mse_export = torch.mean((exported.double() - target.double()) ** 2).item()
+    out = {"workload": f"loop{W}x{H}_n{n}_k{k}", "steps": T, "seconds": gpu_s,
+           "wall_seconds": wall, "ms_per_step": gpu_s * 1e3 / T,
+           "pixel_strokes_per_s": W * H * n * T / gpu_s, "side_slots": slots,
+           "sizing_pass_seconds": t_checked, "timed_equals_sizing_pass": bool(same),
+           "loss_first": losses[0], "loss_last": losses[-1],
+           "hard_mse_initial": mse0, "hard_mse_final": mse1, "hard_mse_exported": mse_export,
+           "paper_context": "240 steps at 1024^2 x 2000: 132 s of step time, 234 s wall, on one "
+                            "RTX PRO 4000 (FP32); different hardware, context only"}
+    del first, loop
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +258,8 @@ def main():
                     help="skip the checkpoint-interval sweep of the fit step")
     ap.add_argument("--no-batched-fit", action="store_true",
                     help="skip the 8-job batched fit comparison")
+    ap.add_argument("--no-fit-loop", action="store_true",
+                    help="skip the 240-step fitting loop")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="length of the Poisson serving replay (0 = skip)")
     ap.add_argument("--serve-warmup", type=float, default=1.0,
@@ -252,8 +316,10 @@ def main():
     # records (an overflowed step skips its update and is repeated)
     for _ in range(args.warmup):
         fit.step_checked(target, headroom=8)
-    slots = fit.opts.side_slots
     recs = fit.tape_records()
+    if fit.opts.side_slots < recs + 8:  # room for the records to grow in the timed steps
+        fit.grow_side_table(recs + 8)
+    slots = fit.opts.side_slots
     log(f"[bench] warmup done; side-table max records {recs}, {slots} slots, "
         f"workspace {fit.nbytes / 2**20:.1f} MiB")
     torch.cuda.empty_cache()
@@ -382,6 +448,9 @@ def main():
     if not args.no_batched_fit:
         out["batched_fit"] = batched_fit_benchmark()
         log(f"[bench] batched fit: {out['batched_fit']}")
+    if not args.no_fit_loop:
+        out["fit_loop"] = fit_loop_benchmark()
+        log(f"[bench] fit loop: {out['fit_loop']}")
     if args.serve_seconds > 0:
         from paper_2609_08722_amd.serve_driver import serving_benchmark
         out["serving"] = serving_benchmark(duration=args.serve_seconds,

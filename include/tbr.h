@@ -211,6 +211,57 @@ tbr_status tbr_fit_multi_records(const tbr_fit_job* jobs, int32_t n_jobs, const 
                                  size_t workspace_bytes, int32_t* max_records, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Fitting loop (Sec. 5.1 "Parameterisation and relaxation", Table hyper,
+ * Sec. 8 "Area budget"). The optimiser works on unconstrained free
+ * parameters theta, packed like the program:
+ *   [th_ax N | th_ay N | th_dx N | th_dy N | th_r N | th_c N*K | th_P K*3].
+ * Windows map them to the program: anchor a = a_lo + (a_hi - a_lo)
+ * sigmoid(th_a) and offset d = l_max tanh(th_d), each per component; the
+ * stroke runs from a to a + d, so m = a + d / 2, L = |d| and
+ * phi = atan2(d_y, d_x) (0 when d = 0); half-width
+ * r = (r_lo_frac + (r_hi_frac - r_lo_frac) sigmoid(th_r)) r0_i with r0_i
+ * geometric from r0_first (stroke 0) to r0_last (stroke N-1); logits
+ * z = th_c; palette P = sigmoid(th_P).
+ * ------------------------------------------------------------------------- */
+typedef struct tbr_window_opts {
+  float a_lo, a_hi;            /* anchor window, a_hi > a_lo (the paper's: the canvas, 0 and 1) */
+  float l_max;                 /* offset bound per component, > 0 (Table hyper: 0.30) */
+  float r0_first, r0_last;     /* > 0 (Table hyper: 0.120 and 0.005) */
+  float r_lo_frac, r_hi_frac;  /* 0 < lo < hi (Table hyper: 0.6 and 1.7) */
+  float lambda_length;         /* lambda sum_i |L_i| (Table hyper: 3e-4), >= 0 */
+  float lambda_area;           /* lambda_A sum_i A_l(r_i), >= 0 */
+} tbr_window_opts;
+
+/* params = window map of theta (device, packed as above / as the program).
+ * TBR_E_INVALID for out-of-range sizes or window options. */
+tbr_status tbr_window_map(int32_t n_strokes, int32_t n_palette, const float* theta, float* params,
+                          const tbr_window_opts* window, void* stream);
+
+/* One step of the fitting loop: params = window map of theta; the fit step's
+ * soft render, L2 seed and replay adjoint (workspace as
+ * tbr_fit_workspace_bytes) give the data loss and its gradient w.r.t. the
+ * program (written to grads, or kept in the workspace if NULL); *loss gets
+ * the data loss plus lambda sum |L| + lambda_A sum A_l(r); the gradient of
+ * that total is chained through the windows and theta takes one Adam step
+ * with the group steps lr_centre (anchor), lr_length (offset), lr_width
+ * (half-width), lr_logits (colour) and lr_palette (palette); lr_angle and
+ * the clamps of tbr_adam_opts are not used. The step's tau and tau_c come
+ * from opts (see tbr_schedule_at). A side-table overflow skips the update
+ * as in tbr_fit_step. */
+tbr_status tbr_fit_loop_step(int32_t n_strokes, int32_t n_palette, float* theta, float* params,
+                             float* grads, float* adam_m, float* adam_v,
+                             const tbr_window_opts* window, const tbr_adam_opts* adam,
+                             const tbr_render_opts* opts, const float* target_rgb, float* loss,
+                             void* workspace, size_t workspace_bytes, void* stream);
+
+/* The schedule of Table hyper at step s of total_steps (host only):
+ * tau and tau_c geometric from first (s = 0) to last (s = total_steps - 1),
+ * and the cosine step factor (1 + cos(pi s / total_steps)) / 2. */
+void tbr_schedule_at(int32_t step, int32_t total_steps, float tau_first, float tau_last,
+                     float tau_c_first, float tau_c_last, float* tau, float* tau_c,
+                     float* lr_scale);
+
+/* ---------------------------------------------------------------------------
  * Serving: continuous batching of replay requests (the forward render above,
  * for many programs, resolutions and modes arriving over time).
  *

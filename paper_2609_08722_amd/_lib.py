@@ -51,6 +51,13 @@ class AdamOpts(C.Structure):
                 ("step", C.c_int32)]
 
 
+class WindowOpts(C.Structure):
+    _fields_ = [("a_lo", C.c_float), ("a_hi", C.c_float), ("l_max", C.c_float),
+                ("r0_first", C.c_float), ("r0_last", C.c_float), ("r_lo_frac", C.c_float),
+                ("r_hi_frac", C.c_float), ("lambda_length", C.c_float),
+                ("lambda_area", C.c_float)]
+
+
 class FitJob(C.Structure):
     _fields_ = [("n_strokes", C.c_int32), ("n_palette", C.c_int32), ("params", C.c_void_p),
                 ("grads", C.c_void_p), ("adam_m", C.c_void_p), ("adam_v", C.c_void_p),
@@ -97,6 +104,11 @@ SIGNATURES = {
     "tbr_fit_multi_workspace_bytes": (_sz, [_vp, _i32]),
     "tbr_fit_multi_step": (_i32, [_vp, _i32, _vp, _sz, _vp]),
     "tbr_fit_multi_records": (_i32, [_vp, _i32, _vp, _sz, _vp, _vp]),
+    "tbr_window_map": (_i32, [_i32, _i32, _vp, _vp, _vp, _vp]),
+    "tbr_fit_loop_step": (_i32, [_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                 _vp, _sz, _vp]),
+    "tbr_schedule_at": (None, [_i32, _i32, C.c_float, C.c_float, C.c_float, C.c_float, _vp, _vp,
+                               _vp]),
     "tbr_serve_program_bytes": (_sz, [_i32, _i32]),
     "tbr_serve_request_bytes": (_sz, [_i32]),
     "tbr_serve_tick_bytes": (_sz, [_vp]),

@@ -254,6 +254,22 @@ tbr_status launch_backward(const tbr_program* p, const tbr_render_opts* o, const
   return launch_reduce(p, o, g, ws, BL, st);
 }
 
+KWindow kwindow_of(const tbr_window_opts* o) {
+  return KWindow{o->a_lo, o->a_hi - o->a_lo, o->l_max, o->r0_first,
+                 (float)std::log((double)o->r0_last / (double)o->r0_first), o->r_lo_frac,
+                 o->r_hi_frac - o->r_lo_frac, o->lambda_length, o->lambda_area};
+}
+
+tbr_status kwindow(const tbr_window_opts* o, KWindow* out) {
+  if (!o) return fail(TBR_E_INVALID, "window opts are NULL");
+  if (!(o->a_hi > o->a_lo) || !(o->l_max > 0.f) || !(o->r0_first > 0.f) || !(o->r0_last > 0.f) ||
+      !(o->r_lo_frac > 0.f) || !(o->r_hi_frac > o->r_lo_frac) || !(o->lambda_length >= 0.f) ||
+      !(o->lambda_area >= 0.f))
+    return fail(TBR_E_INVALID, "window opts out of range");
+  *out = kwindow_of(o);
+  return TBR_OK;
+}
+
 KAdam kadam(const tbr_adam_opts* adam) {
   return KAdam{adam->lr_centre, adam->lr_angle, adam->lr_length, adam->lr_width, adam->lr_logits,
                adam->lr_palette, adam->beta1, adam->beta2, adam->eps,
@@ -277,6 +293,62 @@ size_t multi_offset(const tbr_fit_job* jobs, int j) {
   for (int q = 0; q < j; ++q)
     off = align_up(off + fit_layout(&jobs[q].opts, jobs[q].n_strokes, jobs[q].n_palette).total);
   return off;
+}
+
+// The fit step up to its gradient: stroke prep, the fused forward + seed +
+// replay launch, the loss and the fixed-order reduction to the natural
+// parameters' gradient (*g_out; grads or the workspace copy). *records is the
+// side-table high-water mark on the device.
+tbr_status fit_core(int32_t n_strokes, int32_t n_palette, float* params, float* grads,
+                    const tbr_render_opts* opts, const float* target_rgb, float* loss,
+                    void* workspace, size_t workspace_bytes, hipStream_t st, float** g_out,
+                    const int32_t** records) {
+  tbr_status s;
+  if (n_strokes < 0 || n_palette < 1 || n_palette > 64)
+    return fail(TBR_E_INVALID, "n_strokes %d / n_palette %d out of range", n_strokes, n_palette);
+  if (!params || !target_rgb || !loss || !workspace) return fail(TBR_E_INVALID, "null argument");
+  if ((s = check_opts(opts, true, true))) return s;
+  FitLayout FL = fit_layout(opts, n_strokes, n_palette);
+  if (workspace_bytes < FL.total)
+    return fail(TBR_E_INVALID, "workspace %zu bytes < required %zu", workspace_bytes, FL.total);
+  char* ws = static_cast<char*>(workspace);
+  char* rws = ws + FL.base_r;
+  char* bws = ws + FL.base_b;
+  const int N = n_strokes, K = n_palette;
+  float* g = grads ? grads : reinterpret_cast<float*>(ws + FL.grads);
+  tbr_program prog{N, K, params, params + N, params + 2 * N, params + 3 * N, params + 4 * N,
+                   params + 5 * N, params + 5 * N + (size_t)N * K};
+  tbr_program_grad pg{g, g + N, g + 2 * N, g + 3 * N, g + 4 * N, g + 5 * N,
+                      g + 5 * N + (size_t)N * K};
+  StrokeRec* recs = reinterpret_cast<StrokeRec*>(rws + FL.r.recs);
+  KTape t = ktape(rws, FL.r, opts, true);
+  if ((s = launch_prep(&prog, opts, recs, t.status, st))) return s;
+  float* lpart = reinterpret_cast<float*>(ws + FL.loss_part);
+  // soft forward with tape, L2 seed and replay adjoint of each tile in one
+  // persistent launch (one drain of the GPU per step instead of two)
+  FitJobsK KJ{};
+  KJ.n_jobs = 1;
+  FitJobK& D = KJ.job[0];
+  D.recs = recs;
+  D.palette = prog.palette;
+  D.target = target_rgb;
+  D.partial = reinterpret_cast<float*>(bws + FL.b.partial);
+  D.loss_part = lpart;
+  D.tape = t;
+  D.n = N;
+  D.width = opts->width;
+  D.height = opts->height;
+  D.tiles_x = tiles_x(opts);
+  D.item0 = 0;
+  KJ.n_items = (int)n_tiles(opts);
+  if ((s = launch_fused(KJ, reinterpret_cast<int*>(ws + FL.cursor), st))) return s;
+  k_loss_final<<<1, 256, 0, st>>>(lpart, (int)n_tiles(opts), 1.0f / (3.0f * (float)n_pixels(opts)),
+                                  loss);
+  if ((s = check_launch("loss_final"))) return s;
+  if ((s = launch_reduce(&prog, opts, &pg, bws, FL.b, st))) return s;
+  *g_out = g;
+  *records = t.status;
+  return TBR_OK;
 }
 
 }  // namespace
@@ -383,55 +455,80 @@ tbr_status tbr_fit_step(int32_t n_strokes, int32_t n_palette, float* params, flo
                         const tbr_render_opts* opts, const float* target_rgb, float* loss,
                         void* workspace, size_t workspace_bytes, void* stream) {
   tbr_status s;
-  if (n_strokes < 0 || n_palette < 1 || n_palette > 64)
-    return fail(TBR_E_INVALID, "n_strokes %d / n_palette %d out of range", n_strokes, n_palette);
   if (!params || !adam_m || !adam_v || !adam || !target_rgb || !loss || !workspace)
     return fail(TBR_E_INVALID, "null argument");
-  if ((s = check_opts(opts, true, true))) return s;
   if ((s = check_adam(adam))) return s;
-  FitLayout FL = fit_layout(opts, n_strokes, n_palette);
-  if (workspace_bytes < FL.total)
-    return fail(TBR_E_INVALID, "workspace %zu bytes < required %zu", workspace_bytes, FL.total);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  char* ws = static_cast<char*>(workspace);
-  char* rws = ws + FL.base_r;
-  char* bws = ws + FL.base_b;
+  float* g = nullptr;
+  const int32_t* records = nullptr;
+  if ((s = fit_core(n_strokes, n_palette, params, grads, opts, target_rgb, loss, workspace,
+                    workspace_bytes, st, &g, &records)))
+    return s;
   const int N = n_strokes, K = n_palette;
-  float* g = grads ? grads : reinterpret_cast<float*>(ws + FL.grads);
-  tbr_program prog{N, K, params, params + N, params + 2 * N, params + 3 * N, params + 4 * N,
-                   params + 5 * N, params + 5 * N + (size_t)N * K};
-  tbr_program_grad pg{g, g + N, g + 2 * N, g + 3 * N, g + 4 * N, g + 5 * N,
-                      g + 5 * N + (size_t)N * K};
-  StrokeRec* recs = reinterpret_cast<StrokeRec*>(rws + FL.r.recs);
-  KTape t = ktape(rws, FL.r, opts, true);
-  if ((s = launch_prep(&prog, opts, recs, t.status, st))) return s;
-  float* lpart = reinterpret_cast<float*>(ws + FL.loss_part);
-  // soft forward with tape, L2 seed and replay adjoint of each tile in one
-  // persistent launch (one drain of the GPU per step instead of two)
-  FitJobsK KJ{};
-  KJ.n_jobs = 1;
-  FitJobK& D = KJ.job[0];
-  D.recs = recs;
-  D.palette = prog.palette;
-  D.target = target_rgb;
-  D.partial = reinterpret_cast<float*>(bws + FL.b.partial);
-  D.loss_part = lpart;
-  D.tape = t;
-  D.n = N;
-  D.width = opts->width;
-  D.height = opts->height;
-  D.tiles_x = tiles_x(opts);
-  D.item0 = 0;
-  KJ.n_items = (int)n_tiles(opts);
-  if ((s = launch_fused(KJ, reinterpret_cast<int*>(ws + FL.cursor), st))) return s;
-  k_loss_final<<<1, 256, 0, st>>>(lpart, (int)n_tiles(opts), 1.0f / (3.0f * (float)n_pixels(opts)),
-                                  loss);
-  if ((s = check_launch("loss_final"))) return s;
-  if ((s = launch_reduce(&prog, opts, &pg, bws, FL.b, st))) return s;
   int total = (int)packed_len(N, K);
   k_adam<<<(total + 255) / 256, 256, 0, st>>>(params, g, adam_m, adam_v, N, K, kadam(adam),
-                                              t.status, opts->side_slots);
+                                              records, opts->side_slots);
   return check_launch("adam");
+}
+
+tbr_status tbr_window_map(int32_t n_strokes, int32_t n_palette, const float* theta, float* params,
+                          const tbr_window_opts* window, void* stream) {
+  tbr_status s;
+  if (n_strokes < 0 || n_palette < 1 || n_palette > 64)
+    return fail(TBR_E_INVALID, "n_strokes %d / n_palette %d out of range", n_strokes, n_palette);
+  if (!theta || !params) return fail(TBR_E_INVALID, "null argument");
+  KWindow w;
+  if ((s = kwindow(window, &w))) return s;
+  const int total = (int)packed_len(n_strokes, n_palette);
+  k_window_map<<<(total + 255) / 256, 256, 0, reinterpret_cast<hipStream_t>(stream)>>>(
+      theta, params, n_strokes, n_palette, w);
+  return check_launch("window_map");
+}
+
+tbr_status tbr_fit_loop_step(int32_t n_strokes, int32_t n_palette, float* theta, float* params,
+                             float* grads, float* adam_m, float* adam_v,
+                             const tbr_window_opts* window, const tbr_adam_opts* adam,
+                             const tbr_render_opts* opts, const float* target_rgb, float* loss,
+                             void* workspace, size_t workspace_bytes, void* stream) {
+  tbr_status s;
+  if (!theta || !params || !adam_m || !adam_v || !adam || !target_rgb || !loss || !workspace)
+    return fail(TBR_E_INVALID, "null argument");
+  if ((s = check_adam(adam))) return s;
+  KWindow w;
+  if ((s = kwindow(window, &w))) return s;
+  // every argument is checked before the first launch, so a rejected call
+  // leaves params untouched
+  if (n_strokes < 0 || n_palette < 1 || n_palette > 64)
+    return fail(TBR_E_INVALID, "n_strokes %d / n_palette %d out of range", n_strokes, n_palette);
+  if ((s = check_opts(opts, true, true))) return s;
+  if (workspace_bytes < fit_layout(opts, n_strokes, n_palette).total)
+    return fail(TBR_E_INVALID, "workspace %zu bytes < required %zu", workspace_bytes,
+                fit_layout(opts, n_strokes, n_palette).total);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int N = n_strokes, K = n_palette;
+  const int total = (int)packed_len(N, K);
+  if ((s = tbr_window_map(N, K, theta, params, window, stream))) return s;
+  float* g = nullptr;
+  const int32_t* records = nullptr;
+  if ((s = fit_core(N, K, params, grads, opts, target_rgb, loss, workspace, workspace_bytes, st,
+                    &g, &records)))
+    return s;
+  k_reg_loss<<<1, 256, 0, st>>>(params, N, w, loss);
+  if ((s = check_launch("reg_loss"))) return s;
+  k_window_adam<<<(total + 255) / 256, 256, 0, st>>>(theta, g, adam_m, adam_v, N, K, w,
+                                                     kadam(adam), records, opts->side_slots);
+  return check_launch("window_adam");
+}
+
+void tbr_schedule_at(int32_t step, int32_t total_steps, float tau_first, float tau_last,
+                     float tau_c_first, float tau_c_last, float* tau, float* tau_c,
+                     float* lr_scale) {
+  const double T = total_steps > 1 ? (double)total_steps : 1.0;
+  const double f = total_steps > 1 ? (double)step / (T - 1.0) : 0.0;
+  if (tau) *tau = (float)((double)tau_first * std::pow((double)tau_last / tau_first, f));
+  if (tau_c)
+    *tau_c = (float)((double)tau_c_first * std::pow((double)tau_c_last / tau_c_first, f));
+  if (lr_scale) *lr_scale = (float)(0.5 * (1.0 + std::cos(3.14159265358979323846 * step / T)));
 }
 
 size_t tbr_fit_multi_workspace_bytes(const tbr_fit_job* jobs, int32_t n_jobs) {

@@ -871,3 +871,132 @@ __global__ void __launch_bounds__(256)
 }
 
 }  // namespace tbr
+
+namespace tbr {
+
+// ---------------------------------------------------------------------------
+// Fitting loop (Sec. 5.1 parameterisation; Table hyper regulariser and
+// schedule; Sec. 8 area budget). Free parameters, packed like the program:
+//   [th_ax N | th_ay N | th_dx N | th_dy N | th_r N | th_c N*K | th_P K*3]
+// with anchor a = a_lo + (a_hi - a_lo) sigmoid(th_a), offset
+// d = l_max tanh(th_d) (componentwise), half-width
+// r = (r_lo_frac + (r_hi_frac - r_lo_frac) sigmoid(th_r)) r0_i with r0_i
+// geometric over the program, logits z = th_c and palette P = sigmoid(th_P).
+// The stroke runs from a to a + d: m = a + d / 2, l = |d|, phi = atan2(d).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float logistic(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+__device__ __forceinline__ float window_r0(const KWindow& w, int i, int n) {
+  return n > 1 ? w.r0_first * expf(w.r0_log_ratio * (float)i / (float)(n - 1)) : w.r0_first;
+}
+
+// One thread per packed entry; the thread of entry i < N also writes the
+// stroke's five geometric parameters.
+__global__ void __launch_bounds__(256)
+    k_window_map(const float* __restrict__ th, float* __restrict__ nat, int n, int kpal,
+                 KWindow w) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = 5 * n + n * kpal + 3 * kpal;
+  if (e >= total) return;
+  if (e < n) {
+    const float ax = w.a_lo + w.a_span * logistic(th[e]);
+    const float ay = w.a_lo + w.a_span * logistic(th[n + e]);
+    const float dx = w.l_max * tanhf(th[2 * n + e]);
+    const float dy = w.l_max * tanhf(th[3 * n + e]);
+    const float len = sqrtf(fmaf(dx, dx, dy * dy));
+    nat[e] = fmaf(0.5f, dx, ax);
+    nat[n + e] = fmaf(0.5f, dy, ay);
+    nat[2 * n + e] = len > 0.f ? atan2f(dy, dx) : 0.f;
+    nat[3 * n + e] = len;
+    nat[4 * n + e] = (w.r_lo_frac + w.r_span_frac * logistic(th[4 * n + e])) * window_r0(w, e, n);
+  } else if (e >= 5 * n && e < 5 * n + n * kpal) {
+    nat[e] = th[e];
+  } else if (e >= 5 * n + n * kpal) {
+    nat[e] = logistic(th[e]);
+  }
+}
+
+// lambda sum_i l_i + lambda_A sum_i A_l(r_i), added to *loss in a fixed
+// order (one block).
+__global__ void k_reg_loss(const float* __restrict__ nat, int n, KWindow w, float* __restrict__ loss) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double l = fabs((double)nat[3 * n + i]), r = nat[4 * n + i];
+    acc += (double)w.lambda_length * l + (double)w.lambda_area * (2.0 * l * r + 3.14159265358979323846 * r * r);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = (float)((double)*loss + red[0]);
+}
+
+__device__ __forceinline__ float adam_update(float p, float g, float& m, float& v, float lr,
+                                             const KAdam& a) {
+  m = fmaf(a.beta1, m, (1.f - a.beta1) * g);
+  v = fmaf(a.beta2, v, (1.f - a.beta2) * g * g);
+  const float mh = m / a.bc1, vh = v / a.bc2;
+  return p - lr * mh / (sqrtf(vh) + a.eps);
+}
+
+// Chain rule of the windows (the data gradient g_nat plus the regularisers'
+// gradient in the natural parameters), then Adam on the free parameters with
+// the group steps lr_centre (anchor), lr_length (offset), lr_width
+// (half-width), lr_logits (colour) and lr_palette (palette). Skipped when the
+// step's side table overflowed (records > capacity), like the fit step.
+__global__ void __launch_bounds__(256)
+    k_window_adam(float* __restrict__ th, const float* __restrict__ g_nat,
+                  float* __restrict__ m, float* __restrict__ v, int n, int kpal, KWindow w,
+                  KAdam a, const int32_t* __restrict__ records, int capacity) {
+  if (records && records[0] > capacity) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = 5 * n + n * kpal + 3 * kpal;
+  if (e >= total) return;
+  if (e < n) {
+    const float sax = logistic(th[e]), say = logistic(th[n + e]);
+    const float tdx = tanhf(th[2 * n + e]), tdy = tanhf(th[3 * n + e]);
+    const float dx = w.l_max * tdx, dy = w.l_max * tdy;
+    const float len = sqrtf(fmaf(dx, dx, dy * dy));
+    const float sr = logistic(th[4 * n + e]);
+    const float c0 = window_r0(w, e, n);
+    const float r = (w.r_lo_frac + w.r_span_frac * sr) * c0;
+    const float gmx = g_nat[e], gmy = g_nat[n + e], gphi = g_nat[2 * n + e];
+    // data term + lambda l + lambda_A A_l(r): dA/dl = 2 r, dA/dr = P_l(r)
+    const float gl = g_nat[3 * n + e] + w.lambda_length + w.lambda_area * 2.f * r;
+    const float gr = g_nat[4 * n + e] + w.lambda_area * fmaf(kTwoPi, r, 2.f * len);
+    float gdx = 0.5f * gmx, gdy = 0.5f * gmy;
+    if (len > 0.f) {  // l = |d|, phi = atan2(d): no direction at a drop
+      const float il = 1.f / len, il2 = il * il;
+      gdx = fmaf(gl * dx, il, fmaf(-gphi * dy, il2, gdx));
+      gdy = fmaf(gl * dy, il, fmaf(gphi * dx, il2, gdy));
+    }
+    const float g5[5] = {gmx * w.a_span * sax * (1.f - sax), gmy * w.a_span * say * (1.f - say),
+                         gdx * w.l_max * (1.f - tdx * tdx), gdy * w.l_max * (1.f - tdy * tdy),
+                         gr * w.r_span_frac * c0 * sr * (1.f - sr)};
+    const float lr5[5] = {a.lr_centre, a.lr_centre, a.lr_length, a.lr_length, a.lr_width};
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const size_t o = (size_t)q * n + e;
+      float mm = m[o], vv = v[o];
+      th[o] = adam_update(th[o], g5[q], mm, vv, lr5[q], a);
+      m[o] = mm;
+      v[o] = vv;
+    }
+  } else if (e >= 5 * n) {
+    const bool pal = e >= 5 * n + n * kpal;
+    float g = g_nat[e];
+    if (pal) {
+      const float s = logistic(th[e]);
+      g *= s * (1.f - s);
+    }
+    float mm = m[e], vv = v[e];
+    th[e] = adam_update(th[e], g, mm, vv, pal ? a.lr_palette : a.lr_logits, a);
+    m[e] = mm;
+    v[e] = vv;
+  }
+}
+
+}  // namespace tbr

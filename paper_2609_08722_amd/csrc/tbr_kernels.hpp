@@ -83,7 +83,19 @@ struct KAdam {
   float r_lo, r_hi, l_max;
 };
 
+// Parameter windows of the fitting loop (derived from tbr_window_opts).
+struct KWindow {
+  float a_lo, a_span, l_max;
+  float r0_first, r0_log_ratio;  // r0_i = r0_first exp(r0_log_ratio i / (N - 1))
+  float r_lo_frac, r_span_frac;
+  float lambda_length, lambda_area;
+};
+
 __global__ void k_stroke_prep(KProgram p, KOpts o, StrokeRec* out, int32_t* status);
+__global__ void k_window_map(const float* th, float* nat, int n, int kpal, KWindow w);
+__global__ void k_reg_loss(const float* nat, int n, KWindow w, float* loss);
+__global__ void k_window_adam(float* th, const float* g_nat, float* m, float* v, int n, int kpal,
+                              KWindow w, KAdam a, const int32_t* records, int capacity);
 __global__ void k_trace_soft(const StrokeRec* recs, int n, int width, int height,
                              const float* palette, float* rgb, KTape tape, KSeed seed);
 __global__ void k_trace_hard(const StrokeRec* recs, int n, int width, int height,

@@ -82,6 +82,29 @@ def batch_job(j: int):
     return w
 
 
+# Fitting loop (Table hyper: 2000 strokes, 8 colours, 240 steps at 1024^2).
+# A program is drawn in free parameters: anchors th_a ~ N(0, 1.2^2), offsets
+# th_d ~ N(0, 0.3^2), half-widths th_r ~ N(0, 0.5^2) inside the windows, a
+# uniform palette index with logit 2, palette th_P ~ N(0, 1.5^2). The initial
+# program uses seed 20, the target program seed 21 (its hard render is the
+# target image).
+LOOP_FIT = {"width": 1024, "height": 1024, "n": 2000, "k": 8, "steps": 240, "seed": 20,
+            "target_seed": 21}
+
+
+def loop_theta(n: int, k: int, seed: int) -> np.ndarray:
+    """Free parameters [th_ax|th_ay|th_dx|th_dy|th_r|th_c|th_P] of a program."""
+    rng = np.random.default_rng(seed)
+    ta = rng.normal(0.0, 1.2, size=2 * n)
+    td = rng.normal(0.0, 0.3, size=2 * n)
+    tr = rng.normal(0.0, 0.5, size=n)
+    idx = rng.integers(0, k, size=n)
+    tc = np.zeros((n, k))
+    tc[np.arange(n), idx] = 2.0
+    tp = rng.normal(0.0, 1.5, size=3 * k)
+    return np.concatenate([ta, td, tr, tc.reshape(-1), tp]).astype(np.float32)
+
+
 def make_program(n: int, k: int, seed: int, dist: StrokeDist = DIST_SMALL,
                  beta: float = 1.0, dtype=np.float32) -> dict:
     """Draw one program of ``n`` capsule strokes over a ``k``-colour palette."""

@@ -103,3 +103,70 @@ def test_fit_step_rejects_bad_adam(lib):
     p = C.cast(buf, C.c_void_p)
     st = lib.tbr_fit_step(10, 4, p, None, p, p, C.byref(a), C.byref(o), p, p, p, 64, None)
     assert st == L.TBR_E_INVALID
+
+
+def test_schedule_matches_the_loop_oracle(lib):
+    """tbr_schedule_at (host) against the FP64 oracle of Table hyper's
+    schedule: geometric temperatures and cosine step factor."""
+    from oracle import fitloop as fl
+    cfg = fl.ScheduleCfg(total_steps=240)
+    tau, tau_c, lr = C.c_float(), C.c_float(), C.c_float()
+    for s in (0, 1, 17, 119, 120, 238, 239):
+        lib.tbr_schedule_at(s, 240, 0.35, 0.02, 1.0, 0.05, C.byref(tau), C.byref(tau_c),
+                            C.byref(lr))
+        want = fl.schedule(s, cfg)
+        assert tau.value == pytest.approx(want[0], rel=2e-7)
+        assert tau_c.value == pytest.approx(want[1], rel=2e-7)
+        assert lr.value == pytest.approx(want[2], rel=2e-7, abs=1e-7)
+    # a one-step schedule stays at the first values with the full step
+    lib.tbr_schedule_at(0, 1, 0.35, 0.02, 1.0, 0.05, C.byref(tau), C.byref(tau_c), C.byref(lr))
+    assert (tau.value, tau_c.value, lr.value) == (pytest.approx(0.35), 1.0, 1.0)
+
+
+def window(**kw):
+    base = dict(a_lo=0.0, a_hi=1.0, l_max=0.3, r0_first=0.12, r0_last=0.005, r_lo_frac=0.6,
+                r_hi_frac=1.7, lambda_length=3e-4, lambda_area=0.0)
+    base.update(kw)
+    return L.WindowOpts(*[base[f] for f, _ in L.WindowOpts._fields_])
+
+
+@pytest.mark.parametrize("bad", [dict(a_hi=0.0), dict(l_max=0.0), dict(r0_first=0.0),
+                                 dict(r0_last=-1.0), dict(r_lo_frac=0.0),
+                                 dict(r_hi_frac=0.5), dict(lambda_length=-1.0),
+                                 dict(lambda_area=float("nan"))])
+def test_loop_entries_reject_bad_windows(lib, bad):
+    w = window(**bad)
+    buf = C.create_string_buffer(64)
+    p = C.cast(buf, C.c_void_p)
+    assert lib.tbr_window_map(10, 4, p, p, C.byref(w), None) == L.TBR_E_INVALID
+    assert b"window" in lib.tbr_last_error()
+    a = L.AdamOpts(0.01, 0.01, 0.01, 0.01, 0.01, 0.01, 0.9, 0.999, 1e-8, 0.002, 0.2, 0.3, 1)
+    st = lib.tbr_fit_loop_step(10, 4, p, p, None, p, p, C.byref(w), C.byref(a), C.byref(opts()),
+                               p, p, p, 64, None)
+    assert st == L.TBR_E_INVALID
+
+
+def test_loop_entries_reject_null_and_sizes(lib):
+    w = window()
+    buf = C.create_string_buffer(64)
+    p = C.cast(buf, C.c_void_p)
+    assert lib.tbr_window_map(-1, 4, p, p, C.byref(w), None) == L.TBR_E_INVALID
+    assert lib.tbr_window_map(10, 0, p, p, C.byref(w), None) == L.TBR_E_INVALID
+    assert lib.tbr_window_map(10, 4, None, p, C.byref(w), None) == L.TBR_E_INVALID
+    assert lib.tbr_window_map(10, 4, p, p, None, None) == L.TBR_E_INVALID
+    a = L.AdamOpts(0.01, 0.01, 0.01, 0.01, 0.01, 0.01, 0.9, 0.999, 1e-8, 0.002, 0.2, 0.3, 0)
+    st = lib.tbr_fit_loop_step(10, 4, p, p, None, p, p, C.byref(w), C.byref(a), C.byref(opts()),
+                               p, p, p, 64, None)
+    assert st == L.TBR_E_INVALID  # Adam step counts from 1
+
+
+def test_loop_step_checks_workspace_before_launching(lib):
+    """A workspace too small is rejected before the window map runs (this
+    process has no GPU: any launch would fail with a device error)."""
+    w = window()
+    buf = C.create_string_buffer(64)
+    p = C.cast(buf, C.c_void_p)
+    a = L.AdamOpts(0.01, 0.01, 0.01, 0.01, 0.01, 0.01, 0.9, 0.999, 1e-8, 0.002, 0.2, 0.3, 1)
+    st = lib.tbr_fit_loop_step(10, 4, p, p, None, p, p, C.byref(w), C.byref(a), C.byref(opts()),
+                               p, p, p, 64, None)
+    assert st == L.TBR_E_INVALID and b"workspace" in lib.tbr_last_error()
