@@ -43,7 +43,7 @@ FLOPS_REPLAY = 291   # replay step: chart, Phi displacement, advance, VJP, wave 
 # HBM bytes per k_fit_fused launch at the bench workload, from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
 # in the same runs; valid only for the kernel sources it was measured on.
-TRAFFIC = {"sha": "0766b694f7d3b895", "bytes": 361.4e6 + 588.0e6}
+TRAFFIC = {"sha": "b1ca4cde4e99bea8", "bytes": 361.9e6 + 588.0e6}
 
 
 def kernel_sha():
@@ -81,10 +81,88 @@ def cpu_baseline(w, prog, target_rgb, budget_s=10.0):
     dt = run(n)
     n = min(P, max(n, int(n * budget_s / max(dt, 1e-3))))
     dt = run(n)
-    return {"value": n * w.n_strokes / dt, "unit": "pixel-stroke/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"FP64 soft forward + adjoint of {n} sampled pixels of the "
-                      f"{w.width}x{w.height} x {w.n_strokes}-stroke workload ({dt:.1f} s)"}
+    cores = oracle.num_threads()
+    out = {"value": n * w.n_strokes / dt, "unit": "pixel-stroke/s", "cores": cores,
+           "kind": "oracle",
+           "sample": f"FP64 soft forward + adjoint of {n} sampled pixels of the "
+                     f"{w.width}x{w.height} x {w.n_strokes}-stroke workload ({dt:.1f} s)"}
+    # the other forms: forward only, one thread, and the 256^2 x 500 workload
+    # on its full canvas (each a few seconds)
+    extra = {}
+    pix = np.sort(np.random.default_rng(3).choice(P, size=n // 2, replace=False))
+    t0 = time.perf_counter()
+    oracle.render(prog, w.width, w.height, tau=w.tau, tau_min=w.tau_min, tau_c=w.tau_c,
+                  eps=w.eps, pixels=pix, hard=False)
+    extra["forward_soft_all_cores"] = len(pix) * w.n_strokes / (time.perf_counter() - t0)
+    oracle.set_num_threads(1)
+    try:
+        n1 = 1024
+        extra["forward_adjoint_1_thread"] = n1 * w.n_strokes / run(n1)
+    finally:
+        oracle.set_num_threads(cores)
+    from paper_2609_08722_amd import synth
+    w1 = synth.WORKLOADS["adj256x256_n500"]
+    p1 = synth.workload_program(w1)
+    t1 = synth.workload_program(w1, seed=w1.target_seed)
+    tgt1 = oracle.render(t1, w1.width, w1.height, soft=False)["hard"]
+    t0 = time.perf_counter()
+    r = oracle.render(p1, w1.width, w1.height, tau=w1.tau, tau_min=w1.tau_min, tau_c=w1.tau_c,
+                      hard=False)
+    oracle.backward(p1, w1.width, w1.height, 2.0 * (r["soft"] - tgt1) / (3.0 * w1.pixels),
+                    tau=w1.tau, tau_min=w1.tau_min, tau_c=w1.tau_c)
+    extra[f"forward_adjoint_full_canvas_{w1.name}"] = w1.pixels * w1.n_strokes / (
+        time.perf_counter() - t0)
+    out["other_forms"] = {k: float(v) for k, v in extra.items()}
+    out["host"] = {"nproc": os.cpu_count(), "cpu": _cpu_model()}
+    return out
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def api_forms(w, prog, opts, target, iters=20, warm=5):
+    """Per-call GPU time of the path's API forms on the same program, with
+    HIP events on the stream around each call (median and min over iters):
+    (i) tbr_render (soft, with tape) + L2 seed + tbr_render_backward,
+    (iii) the soft forward alone (no tape) and the hard forward alone.
+    The fused fit step (ii) is the main figure."""
+    import torch
+    from paper_2609_08722_amd import api
+    P, N = w.pixels, w.n_strokes
+    stream = torch.cuda.current_stream()
+
+    def fwd_bwd():
+        R = api.render(prog, opts, "soft", tape=True, check_overflow=False)
+        seed = (R["rgb"] - target) * (2.0 / (3.0 * P))
+        api.render_backward(prog, R["tape"], seed)
+
+    forms = {"render_tape_plus_backward": fwd_bwd,
+             "forward_soft": lambda: api.render(prog, opts, "soft"),
+             "forward_hard": lambda: api.render(prog, opts, "hard")}
+    out = {}
+    for name, fn in forms.items():
+        for _ in range(warm):
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(iters)]
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        t = np.array([a.elapsed_time(b) for a, b in ev])
+        out[name] = {"median_ms": float(np.median(t)), "min_ms": float(t.min()),
+                     "pixel_strokes_per_s": P * N / (np.median(t) * 1e-3)}
+    return out
 
 
 def ckpt_baseline(w, dprog, target, every=50, steps=2):
@@ -336,11 +414,15 @@ def main():
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    step_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
     start.record(stream)
     for s in range(args.steps):
         a, b = ev[s]
         L.check(lib.tbr_set_timing_events(b"fit_fused", a.cuda_event, b.cuda_event))
+        step_ev[s][0].record(stream)
         fit.step(target)
+        step_ev[s][1].record(stream)
     stop.record(stream)
     torch.cuda.synchronize()
     lib.tbr_set_timing_events(None, None, None)
@@ -350,7 +432,9 @@ def main():
         log("[bench] WARNING: the side table overflowed during the timed steps")
     ms = start.elapsed_time(stop) / args.steps
     ms_fused = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    step_t = np.array([a.elapsed_time(b) for a, b in step_ev])
     peak = torch.cuda.max_memory_allocated()
+    free_b, total_b = torch.cuda.mem_get_info()  # hipMemGetInfo: the device's own view
     loss = float(fit.loss.item())
     value = P * N / (ms * 1e-3)
     log(f"[bench] {ms:.3f} ms/step; fused forward + replay {ms_fused:.3f} ms; "
@@ -410,6 +494,16 @@ def main():
     except Exception as e:  # reported, never hides the main figure
         log(f"[bench] hard render timing failed: {e}")
 
+    forms = {}
+    try:
+        forms = api_forms(w, cur, opts, target)
+        forms["fused_fit_step"] = {"median_ms": float(np.median(step_t)),
+                                   "min_ms": float(step_t.min()),
+                                   "pixel_strokes_per_s": P * N / (np.median(step_t) * 1e-3)}
+    except Exception as e:  # reported, never hides the main figure
+        log(f"[bench] API form timing failed: {e}")
+    log(f"[bench] API forms: {forms}")
+
     out = {
         "metric": "pixel-stroke evals/s (soft fwd+adjoint, 1024^2 x 2000)",
         "value": value, "unit": "pixel-stroke/s", "n_gpus": 1, "steps": args.steps,
@@ -430,7 +524,10 @@ def main():
                             ("k_replay", FLOPS_REPLAY, "replay"))},
         "step_fp32_peak_frac": flops * P * N / (ms * 1e-3) / PEAK_FP32_FLOPS,
         "hard_render_ms": hard_ms,
+        "api_forms": forms,
+        "step_ms_median": float(np.median(step_t)), "step_ms_min": float(step_t.min()),
         "peak_hbm_bytes": int(peak),
+        "device_bytes_in_use_after_steps": int(total_b - free_b),
         "side_table_max_records": int(recs),
         "timed_steps_overflowed": bool(overflowed),
         "loss_after_steps": loss,
