@@ -39,7 +39,7 @@ class OrcOpts(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32),
                 ("tau", C.c_double), ("tau_min", C.c_double),
                 ("tau_c", C.c_double), ("eps", C.c_double),
-                ("transport", C.c_int32)]
+                ("transport", C.c_int32), ("coupling", C.c_void_p)]
 
 
 def _load():
@@ -49,10 +49,10 @@ def _load():
             build(force=False)
         _lib = C.CDLL(_LIB)
         vp, i64, dbl, i32 = C.c_void_p, C.c_int64, C.c_double, C.c_int
-        _lib.orc_psi.argtypes = [vp, dbl, i64, vp, vp, vp]
-        _lib.orc_phi.argtypes = [vp, i64, vp, vp]
-        _lib.orc_chart.argtypes = [vp, i64, vp, vp, vp]
-        _lib.orc_map_jacobian.argtypes = [i32, vp, dbl, i64, vp, vp]
+        _lib.orc_psi.argtypes = [vp, dbl, i64, vp, vp, vp, vp]
+        _lib.orc_phi.argtypes = [vp, i64, vp, vp, vp]
+        _lib.orc_chart.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+        _lib.orc_map_jacobian.argtypes = [i32, vp, dbl, i64, vp, vp, vp]
         _lib.orc_render.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
         _lib.orc_render.restype = i32
         _lib.orc_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
@@ -84,43 +84,54 @@ def _stroke(stroke):
     return s
 
 
-def psi(stroke, pts, eps=1e-3):
-    """Backward map of one stroke (m_x, m_y, phi, L, r) at points [n,2]."""
+def _coup(coupling):
+    return None if coupling is None else _f64(coupling).reshape(3)
+
+
+def psi(stroke, pts, eps=1e-3, coupling=None):
+    """Backward map of one stroke (m_x, m_y, phi, L, r) at points [n,2];
+    coupling = (c_1, c_2, c_3) of the calibrated variant, or None."""
     s = _stroke(stroke)
     p = _f64(pts).reshape(-1, 2)
+    c = _coup(coupling)
     out = np.empty_like(p)
     rec = np.empty(len(p), dtype=np.int32)
-    _load().orc_psi(_ptr(s), float(eps), len(p), _ptr(p), _ptr(out), _ptr(rec))
+    _load().orc_psi(_ptr(s), float(eps), len(p), _ptr(p), _ptr(out), _ptr(rec), _ptr(c))
     return out, rec.astype(bool)
 
 
-def phi(stroke, pts):
+def phi(stroke, pts, coupling=None):
     """Exterior forward map of one stroke at points [n,2]."""
     s = _stroke(stroke)
     p = _f64(pts).reshape(-1, 2)
+    c = _coup(coupling)
     out = np.empty_like(p)
-    _load().orc_phi(_ptr(s), len(p), _ptr(p), _ptr(out))
+    _load().orc_phi(_ptr(s), len(p), _ptr(p), _ptr(out), _ptr(c))
     return out
 
 
-def chart(stroke, pts):
-    """(sigma, w): distance to the segment and centred arclength fraction."""
+def chart(stroke, pts, coupling=None, edge=False):
+    """(sigma, w): distance to the segment and centred arclength fraction;
+    with edge=True also the deposit's edge on each point's leaf."""
     s = _stroke(stroke)
     p = _f64(pts).reshape(-1, 2)
+    c = _coup(coupling)
     sig = np.empty(len(p))
     w = np.empty(len(p))
-    _load().orc_chart(_ptr(s), len(p), _ptr(p), _ptr(sig), _ptr(w))
-    return sig, w
+    e = np.empty(len(p)) if edge else None
+    _load().orc_chart(_ptr(s), len(p), _ptr(p), _ptr(sig), _ptr(w), _ptr(e), _ptr(c))
+    return (sig, w, e) if edge else (sig, w)
 
 
-def map_jacobian(which, stroke, pts, eps=1e-3):
+def map_jacobian(which, stroke, pts, eps=1e-3, coupling=None):
     """Exact Jacobian [n,2,7] of psi ('psi') or Phi ('phi') w.r.t.
     (x, y, m_x, m_y, phi, L, r)."""
     s = _stroke(stroke)
     p = _f64(pts).reshape(-1, 2)
+    c = _coup(coupling)
     jac = np.empty((len(p), 2, 7))
     _load().orc_map_jacobian(0 if which == "psi" else 1, _ptr(s), float(eps), len(p),
-                             _ptr(p), _ptr(jac))
+                             _ptr(p), _ptr(jac), _ptr(c))
     return jac
 
 
@@ -139,20 +150,32 @@ class _Prog:
         self.n, self.k = n, k
 
 
-def _opts(width, height, tau, tau_min, tau_c, eps, transport):
+class _Coupling:
+    """Holds the FP64 [N][3] coefficient copy alive for the duration of a call."""
+
+    def __init__(self, coupling, n):
+        self.arr = None if coupling is None else _f64(coupling).reshape(n, 3)
+
+    def ptr(self):
+        return _ptr(self.arr)
+
+
+def _opts(width, height, tau, tau_min, tau_c, eps, transport, coup=None):
     return OrcOpts(int(width), int(height), float(tau), float(tau_min), float(tau_c),
-                   float(eps), int(transport))
+                   float(eps), int(transport), None if coup is None else coup.ptr())
 
 
 def render(prog, width, height, *, tau=1e-3, tau_min=None, tau_c=0.0, eps=1e-3,
-           transport=True, pixels=None, soft=True, hard=True):
+           transport=True, pixels=None, soft=True, hard=True, coupling=None):
     """Render a program (dict of arrays, see the synthetic generator) at pixel
     centres. Returns a dict with 'soft' [n,3], 'hard' [n,3], 'label', 'owner',
-    'dmin', 'n_rec' (flat pixel order, or the order of ``pixels``)."""
+    'dmin', 'n_rec' (flat pixel order, or the order of ``pixels``).
+    coupling: [N,3] c_1..c_3 per stroke of the calibrated variant, or None."""
     if tau_min is None:
         tau_min = 0.7 / width
     pr = _Prog(prog)
-    o = _opts(width, height, tau, tau_min, tau_c, eps, transport)
+    cp = _Coupling(coupling, pr.n)
+    o = _opts(width, height, tau, tau_min, tau_c, eps, transport, cp)
     pix = None if pixels is None else np.ascontiguousarray(np.asarray(pixels, dtype=np.int64))
     n = width * height if pix is None else len(pix)
     out = {}
@@ -171,14 +194,16 @@ def render(prog, width, height, *, tau=1e-3, tau_min=None, tau_c=0.0, eps=1e-3,
 
 
 def backward(prog, width, height, grad_rgb, *, tau=1e-3, tau_min=None, tau_c=0.0, eps=1e-3,
-             transport=True, pixels=None):
+             transport=True, pixels=None, coupling=None):
     """Vector-Jacobian product of the soft render with grad_rgb [n,3].
     Returns dict: 'geom' [5,N] (m_x, m_y, phi, L, r), 'colour' [N,3],
-    'logits' [N,K], 'palette' [K,3]."""
+    'logits' [N,K], 'palette' [K,3]. The coupling coefficients are
+    constants (no gradient)."""
     if tau_min is None:
         tau_min = 0.7 / width
     pr = _Prog(prog)
-    o = _opts(width, height, tau, tau_min, tau_c, eps, transport)
+    cp = _Coupling(coupling, pr.n)
+    o = _opts(width, height, tau, tau_min, tau_c, eps, transport, cp)
     pix = None if pixels is None else np.ascontiguousarray(np.asarray(pixels, dtype=np.int64))
     n = width * height if pix is None else len(pix)
     g = _f64(grad_rgb).reshape(n, 3)
@@ -191,10 +216,11 @@ def backward(prog, width, height, grad_rgb, *, tau=1e-3, tau_min=None, tau_c=0.0
     return {"geom": geom, "colour": colour, "logits": logits, "palette": palette}
 
 
-def hard_points(prog, pts, *, eps=1e-3, transport=True):
+def hard_points(prog, pts, *, eps=1e-3, transport=True, coupling=None):
     """Owner (0-based stroke index or -1) of arbitrary final-plane points."""
     pr = _Prog(prog)
-    o = _opts(1, 1, 1e-3, 1e-3, 0.0, eps, transport)
+    cp = _Coupling(coupling, pr.n)
+    o = _opts(1, 1, 1e-3, 1e-3, 0.0, eps, transport, cp)
     p = _f64(pts).reshape(-1, 2)
     own = np.empty(len(p), dtype=np.int32)
     _load().orc_hard_points(C.byref(pr.s), C.byref(o), len(p), _ptr(p), _ptr(own))

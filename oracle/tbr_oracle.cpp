@@ -15,6 +15,10 @@
 //     Prop. (centred arclength), Eq. (back), Eq. (fwd);
 //   * extension into the footprint and the implemented floor C >= (eps r)^2
 //     with its record rule: Sec. 4 "The chain", Sec. 5.2 after the Lemma;
+//   * the calibrated variant Phi_g (Sec. 4, "A variant closer to line-source
+//     potential flow", Eq. coupling, Eq. profile): the area added along the
+//     leaf of centred fraction v is A_l(r) g(v), g(v) = 1 + sum_k c_k
+//     cos(4 pi k v), and the deposit is {u <= A_l(r) g(v)};
 //   * soft coverage: Sec. 5.1, Eq. (relax); alpha clamp 1 - 1e-7: Sec. 5.2;
 //   * colour model c = softmax(z / tau_c) P: Sec. 5.1;
 //   * gradient: plain reverse-mode chain rule over the state of Eq. (state),
@@ -128,6 +132,7 @@ inline Dual m_atan2(const Dual& y, const Dual& x) {
 template <class T>
 struct Stroke {
   T mx, my, phi, L, r;
+  const double* coup = nullptr;  // c_1..c_3 of Eq. profile (constants), or none: g = 1
 };
 
 // Chart coordinates of a point with respect to a stroke (Sec. 4):
@@ -192,16 +197,50 @@ void reconstruct(const Chart<T>& c, const Stroke<T>& g, const T& rho, T& ox, T& 
   oy = g.my + a * c.se + b * c.ce;
 }
 
+// Steiner area of the parallel set, Eq. (steiner): A = 2 l sigma + pi sigma^2.
+template <class T>
+T steiner_area(const T& ell, const T& sigma) {
+  return (2.0 * ell + kPi * sigma) * sigma;
+}
+
+// Eq. (profile): g(v) = 1 + sum_{k=1..3} c_k cos(4 pi k v).
+template <class T>
+T profile(const T& v, const double* c) {
+  T g = T(1.0);
+  for (int k = 1; k <= 3; ++k) g = g + c[k - 1] * m_cos(4.0 * kPi * double(k) * v);
+  return g;
+}
+
+// Area the stroke inserts along the leaf of the charted point: A_l(r), or
+// A_l(r) g(v) under the calibrated coupling (Eq. coupling).
+template <class T>
+T leaf_area(const Chart<T>& c, const Stroke<T>& g) {
+  T A = steiner_area(c.ell, g.r);
+  return g.coup ? A * profile(c.w, g.coup) : A;
+}
+
+// Distance at which the deposit ends on the point's leaf: r, or the root of
+// A_l(rho) = A_l(r) g(v) (the deposit {u <= A_l(r) g(v)} of Eq. coupling).
+template <class T>
+T leaf_edge(const Chart<T>& c, const Stroke<T>& g) {
+  if (!g.coup) return g.r;
+  T G = leaf_area(c, g);
+  return G / (c.ell + m_sqrt(c.ell * c.ell + kPi * G));
+}
+
 // psi: backward material map of one stroke, Eq. (back), with the implemented
 // floor C >= (eps r)^2 (eps = 0 gives the ideal clamp C -> 0). Returns
 // whether the floor bound (the record rule C < (eps r)^2).
 template <class T>
 bool psi(const T& x, const T& y, const Stroke<T>& g, double eps, T& ox, T& oy,
-         T* sigma_out = nullptr) {
+         T* sigma_out = nullptr, T* edge_out = nullptr) {
   Chart<T> c = chart(x, y, g);
   if (sigma_out) *sigma_out = c.sigma;
-  // C = A_l(sigma') - A_l(r) in factored form.
-  T C = (c.sigma - g.r) * (2.0 * c.ell + kPi * (c.sigma + g.r));
+  if (edge_out) *edge_out = leaf_edge(c, g);
+  // C = A_l(sigma') - A_l(r) in factored form; under the coupling the
+  // subtracted area is A_l(r) g(v), written as the plain difference.
+  T C = g.coup ? steiner_area(c.ell, c.sigma) - leaf_area(c, g)
+               : (c.sigma - g.r) * (2.0 * c.ell + kPi * (c.sigma + g.r));
   T fl = (eps * g.r) * (eps * g.r);
   bool rec = val(C) < val(fl);
   if (rec) C = fl;
@@ -215,16 +254,19 @@ bool psi(const T& x, const T& y, const Stroke<T>& g, double eps, T& ox, T& oy,
 template <class T>
 void phi_map(const T& x, const T& y, const Stroke<T>& g, T& ox, T& oy) {
   Chart<T> c = chart(x, y, g);
-  T B = 2.0 * c.ell * (c.sigma + g.r) + kPi * (c.sigma * c.sigma + g.r * g.r);
+  T B = g.coup ? steiner_area(c.ell, c.sigma) + leaf_area(c, g)
+               : 2.0 * c.ell * (c.sigma + g.r) + kPi * (c.sigma * c.sigma + g.r * g.r);
   T sp = B / (c.ell + m_sqrt(c.ell * c.ell + kPi * B));
   reconstruct(c, g, sp, ox, oy);
 }
 
-// Soft coverage, Eq. (relax), clamped at 1 - 1e-7.
+// Soft coverage, Eq. (relax), clamped at 1 - 1e-7: the signed distance from
+// the deposit's edge on the point's leaf (r, or the coupled leaf_edge) over
+// the width max(tau r, tau_min) of the stroke's half-width r.
 template <class T>
-T soft_alpha(const T& sigma, const T& r, double tau, double tau_min) {
+T soft_alpha(const T& sigma, const T& edge, const T& r, double tau, double tau_min) {
   T wd = val(r) * tau > tau_min ? tau * r : T(tau_min);
-  T z = (r - sigma) / wd;
+  T z = (edge - sigma) / wd;
   // The logistic function, written so that the exponential never overflows
   // (far pixels reach z < -709): e^z / (1 + e^z) for z < 0.
   T a;
@@ -249,11 +291,14 @@ struct Program {
 struct Opts {
   int32_t width, height;
   double tau, tau_min, tau_c, eps;
-  int32_t transport;  // 1 = displacing renderer R_A, 0 = inert-mark R_U
+  int32_t transport;       // 1 = displacing renderer R_A, 0 = inert-mark R_U
+  const double* coupling;  // [N][3] c_1..c_3 per stroke (Eq. profile), or NULL: g = 1
 };
 
-Stroke<double> stroke_at(const Program& p, int i) {
-  return {p.cx[i], p.cy[i], p.angle[i], p.length[i], p.half_width[i]};
+Stroke<double> stroke_at(const Program& p, const Opts& o, int i) {
+  Stroke<double> g{p.cx[i], p.cy[i], p.angle[i], p.length[i], p.half_width[i]};
+  g.coup = o.coupling ? o.coupling + 3 * size_t(i) : nullptr;
+  return g;
 }
 
 int argmax_row(const double* z, int k) {
@@ -310,44 +355,53 @@ typedef struct {
   int32_t width, height;
   double tau, tau_min, tau_c, eps;
   int32_t transport;
+  const double* coupling;
 } orc_opts;
 
 static Program to_prog(const orc_program* p) {
   return {p->n, p->k, p->cx, p->cy, p->angle, p->length, p->half_width, p->logits, p->palette};
 }
 static Opts to_opts(const orc_opts* o) {
-  return {o->width, o->height, o->tau, o->tau_min, o->tau_c, o->eps, o->transport};
+  return {o->width, o->height, o->tau, o->tau_min, o->tau_c, o->eps, o->transport, o->coupling};
 }
 
 // psi for a batch of points; stroke = (m_x, m_y, phi, L, r).
+// coup: c_1..c_3 of the calibrated coupling, or NULL (uniform insertion).
 void orc_psi(const double* stroke, double eps, int64_t n, const double* pts, double* out,
-             int32_t* rec) {
+             int32_t* rec, const double* coup) {
   Stroke<double> g{stroke[0], stroke[1], stroke[2], stroke[3], stroke[4]};
+  g.coup = coup;
   for (int64_t j = 0; j < n; ++j) {
     bool b = psi(pts[2 * j], pts[2 * j + 1], g, eps, out[2 * j], out[2 * j + 1]);
     if (rec) rec[j] = b ? 1 : 0;
   }
 }
 
-void orc_phi(const double* stroke, int64_t n, const double* pts, double* out) {
+void orc_phi(const double* stroke, int64_t n, const double* pts, double* out,
+             const double* coup) {
   Stroke<double> g{stroke[0], stroke[1], stroke[2], stroke[3], stroke[4]};
+  g.coup = coup;
   for (int64_t j = 0; j < n; ++j) phi_map(pts[2 * j], pts[2 * j + 1], g, out[2 * j], out[2 * j + 1]);
 }
 
-// Distance to the segment and centred arclength fraction (diagnostics).
-void orc_chart(const double* stroke, int64_t n, const double* pts, double* sigma, double* w) {
+// Distance to the segment, centred arclength fraction and the deposit's
+// edge on the point's leaf (diagnostics; edge may be NULL).
+void orc_chart(const double* stroke, int64_t n, const double* pts, double* sigma, double* w,
+               double* edge, const double* coup) {
   Stroke<double> g{stroke[0], stroke[1], stroke[2], stroke[3], stroke[4]};
+  g.coup = coup;
   for (int64_t j = 0; j < n; ++j) {
     Chart<double> c = chart(pts[2 * j], pts[2 * j + 1], g);
     sigma[j] = c.sigma;
     w[j] = c.w;
+    if (edge) edge[j] = leaf_edge(c, g);
   }
 }
 
 // Exact Jacobians (dual numbers) of psi (which = 0) or Phi (which = 1):
 // jac[j] is 2 x 7, row-major, columns (x, y, m_x, m_y, phi, L, r).
 void orc_map_jacobian(int which, const double* stroke, double eps, int64_t n, const double* pts,
-                      double* jac) {
+                      double* jac, const double* coup) {
   for (int64_t j = 0; j < n; ++j) {
     Dual x(pts[2 * j]), y(pts[2 * j + 1]);
     x.d[0] = 1;
@@ -363,6 +417,7 @@ void orc_map_jacobian(int which, const double* stroke, double eps, int64_t n, co
     g.L.d[5] = 1;
     g.r = Dual(stroke[4]);
     g.r.d[6] = 1;
+    g.coup = coup;
     Dual ox, oy;
     if (which == 0)
       psi(x, y, g, eps, ox, oy);
@@ -401,10 +456,10 @@ int orc_render(const orc_program* prog, const orc_opts* opts, int64_t n_pix, con
       double x = x0, y = y0, C[3] = {0, 0, 0}, T = 1.0;
       int32_t nr = 0;
       for (int i = p.n - 1; i >= 0; --i) {
-        Stroke<double> g = stroke_at(p, i);
-        double ox, oy, sig;
-        bool rec = psi(x, y, g, o.eps, ox, oy, &sig);
-        double a = soft_alpha(sig, g.r, o.tau, o.tau_min);
+        Stroke<double> g = stroke_at(p, o, i);
+        double ox, oy, sig, edge;
+        bool rec = psi(x, y, g, o.eps, ox, oy, &sig, &edge);
+        double a = soft_alpha(sig, edge, g.r, o.tau, o.tau_min);
         for (int ch = 0; ch < 3; ++ch) C[ch] += T * a * col[size_t(i) * 3 + ch];
         T *= (1.0 - a);
         nr += rec ? 1 : 0;
@@ -421,10 +476,11 @@ int orc_render(const orc_program* prog, const orc_opts* opts, int64_t n_pix, con
       double x = x0, y = y0, dm = INFINITY;
       int own = -1;
       for (int i = p.n - 1; i >= 0; --i) {
-        Stroke<double> g = stroke_at(p, i);
+        Stroke<double> g = stroke_at(p, o, i);
         Chart<double> c = chart(x, y, g);
-        dm = std::min(dm, std::fabs(c.sigma - g.r));
-        if (c.sigma <= g.r) {  // closed footprint
+        const double edge = leaf_edge(c, g);
+        dm = std::min(dm, std::fabs(c.sigma - edge));
+        if (c.sigma <= edge) {  // closed footprint
           own = i;
           break;
         }
@@ -489,10 +545,10 @@ int orc_backward(const orc_program* prog, const orc_opts* opts, int64_t n_pix, c
         xs[2 * N + 1] = y;
         Ts[N] = 1.0;
         for (int i = N; i >= 1; --i) {
-          Stroke<double> g = stroke_at(p, i - 1);
-          double ox, oy, sig;
-          psi(x, y, g, o.eps, ox, oy, &sig);
-          double a = soft_alpha(sig, g.r, o.tau, o.tau_min);
+          Stroke<double> g = stroke_at(p, o, i - 1);
+          double ox, oy, sig, edge;
+          psi(x, y, g, o.eps, ox, oy, &sig, &edge);
+          double a = soft_alpha(sig, edge, g.r, o.tau, o.tau_min);
           T *= (1.0 - a);
           if (o.transport) {
             x = ox;
@@ -510,7 +566,7 @@ int orc_backward(const orc_program* prog, const orc_opts* opts, int64_t n_pix, c
         // Reverse over steps i = 1..N (s_i -> s_{i-1}).
         for (int i = 1; i <= N; ++i) {
           const int si = i - 1;
-          Stroke<double> gd = stroke_at(p, si);
+          Stroke<double> gd = stroke_at(p, o, si);
           Dual X(xs[2 * i]), Y(xs[2 * i + 1]);
           X.d[0] = 1;
           Y.d[1] = 1;
@@ -525,9 +581,10 @@ int orc_backward(const orc_program* prog, const orc_opts* opts, int64_t n_pix, c
           g.L.d[5] = 1;
           g.r = Dual(gd.r);
           g.r.d[6] = 1;
-          Dual ox, oy, sig;
-          psi(X, Y, g, o.eps, ox, oy, &sig);
-          Dual a = soft_alpha(sig, g.r, o.tau, o.tau_min);
+          g.coup = gd.coup;
+          Dual ox, oy, sig, edge;
+          psi(X, Y, g, o.eps, ox, oy, &sig, &edge);
+          Dual a = soft_alpha(sig, edge, g.r, o.tau, o.tau_min);
           if (!o.transport) {  // psi = id
             ox = X;
             oy = Y;
@@ -593,9 +650,9 @@ void orc_hard_points(const orc_program* prog, const orc_opts* opts, int64_t n, c
     double x = pts[2 * j], y = pts[2 * j + 1];
     int own = -1;
     for (int i = p.n - 1; i >= 0; --i) {
-      Stroke<double> g = stroke_at(p, i);
+      Stroke<double> g = stroke_at(p, o, i);
       Chart<double> c = chart(x, y, g);
-      if (c.sigma <= g.r) {
+      if (c.sigma <= leaf_edge(c, g)) {
         own = i;
         break;
       }
