@@ -88,6 +88,24 @@ typedef struct tbr_program_grad {
   float* palette;
 } tbr_program_grad;
 
+/* Transport of a stroke (the insertion map every render, adjoint and fit
+ * step applies).
+ *   TBR_TRANSPORT_CAPSULE: the capsule insertion operator of Sec. 4
+ *     (Eq. phi / Eq. back / Eq. fwd): every leaf of the area chart receives
+ *     the area A_l(r) and the deposit is {sigma' <= r}.
+ *   TBR_TRANSPORT_COUPLED: the calibrated variant of Sec. 4 ("A variant
+ *     closer to line-source potential flow", Eq. coupling, Eq. profile): the
+ *     leaf of centred arclength fraction v receives A_l(r) g(v), with
+ *     g(v) = 1 + c_1 cos 4 pi v + c_2 cos 8 pi v + c_3 cos 12 pi v per
+ *     stroke; the deposit is {u <= A_l(r) g(v)}, i.e. sigma' <= rl(v) with
+ *     A_l(rl) = A_l(r) g(v). The hard footprint and the soft coverage
+ *     sigmoid((rl(v) - sigma') / max(tau r, tau_min)) use that edge; the
+ *     floor stays (eps r)^2. The coefficients are constants of the call:
+ *     no gradient flows to them. g must be positive on every leaf (check a
+ *     coefficient table with tbr_coupling_check); where it is not, the
+ *     kernels take g = 0 and the result is meaningless. */
+enum { TBR_TRANSPORT_CAPSULE = 0, TBR_TRANSPORT_COUPLED = 1 };
+
 typedef struct tbr_render_opts {
   int32_t width, height;  /* 1 .. 16384 each */
   float tau;              /* relative relaxation width, >= 0 (Eq. relax) */
@@ -96,7 +114,17 @@ typedef struct tbr_render_opts {
   float eps_floor;        /* floor constant eps of C >= (eps r)^2, > 0 (paper: 1e-3) */
   int32_t ckpt_interval;  /* position checkpoint interval k of the adjoint, >= 0 (0 = none) */
   int32_t side_slots;     /* per-pixel side-table capacity, >= 1 when a tape is written */
+  int32_t transport;      /* TBR_TRANSPORT_CAPSULE (0) or TBR_TRANSPORT_COUPLED */
+  const float* coupling;  /* COUPLED: device [n_strokes * 3], (c_1, c_2, c_3) per stroke, read
+                             by the call's stroke preparation; otherwise ignored (may be NULL) */
 } tbr_render_opts;
+
+/* Exact positivity check of the coupled profiles (Sec. 4: g is a cubic in
+ * cos 4 pi v on [-1, 1], so its minimum is at an end or at a root of its
+ * derivative). coupling: HOST [n_strokes * 3]. Writes the smallest value of
+ * g over all strokes and leaves to *min_g (may be NULL; 1 when n_strokes is
+ * 0). TBR_E_INVALID if it is not > 0 (or a coefficient is not finite). */
+tbr_status tbr_coupling_check(const float* coupling, int32_t n_strokes, float* min_g);
 
 /* Per-group Adam settings for tbr_fit_step (Sec. 5.1, Table hyper). */
 typedef struct tbr_adam_opts {

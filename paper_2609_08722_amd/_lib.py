@@ -12,6 +12,7 @@ TBR_OK, TBR_PENDING = 0, 1
 TBR_E_INVALID, TBR_E_NOMEM, TBR_E_OVERFLOW, TBR_E_CAPACITY = -1, -2, -3, -4
 TBR_E_DEVICE, TBR_E_CANCELLED, TBR_E_NOTFOUND = -5, -6, -7
 TBR_HARD, TBR_SOFT = 1, 2
+TBR_TRANSPORT_CAPSULE, TBR_TRANSPORT_COUPLED = 0, 1
 
 STATUS_NAMES = {0: "TBR_OK", 1: "TBR_PENDING", -1: "TBR_E_INVALID", -2: "TBR_E_NOMEM",
                 -3: "TBR_E_OVERFLOW", -4: "TBR_E_CAPACITY", -5: "TBR_E_DEVICE",
@@ -40,7 +41,8 @@ class ProgramGrad(C.Structure):
 class RenderOpts(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("tau", C.c_float),
                 ("tau_min", C.c_float), ("tau_c", C.c_float), ("eps_floor", C.c_float),
-                ("ckpt_interval", C.c_int32), ("side_slots", C.c_int32)]
+                ("ckpt_interval", C.c_int32), ("side_slots", C.c_int32),
+                ("transport", C.c_int32), ("coupling", C.c_void_p)]
 
 
 class AdamOpts(C.Structure):
@@ -104,6 +106,7 @@ SIGNATURES = {
     "tbr_fit_multi_workspace_bytes": (_sz, [_vp, _i32]),
     "tbr_fit_multi_step": (_i32, [_vp, _i32, _vp, _sz, _vp]),
     "tbr_fit_multi_records": (_i32, [_vp, _i32, _vp, _sz, _vp, _vp]),
+    "tbr_coupling_check": (_i32, [_vp, _i32, _vp]),
     "tbr_window_map": (_i32, [_i32, _i32, _vp, _vp, _vp, _vp]),
     "tbr_fit_loop_step": (_i32, [_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                  _vp, _sz, _vp]),

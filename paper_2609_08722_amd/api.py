@@ -34,16 +34,39 @@ class Opts:
     eps: float = 1e-3
     ckpt: int = 256
     side_slots: int = 16
+    # calibrated coupling (Eq. coupling, Eq. profile): a contiguous float32
+    # CUDA tensor [N, 3] of (c_1, c_2, c_3) per stroke, or None (capsule map)
+    coupling: "torch.Tensor | None" = None
 
-    def c(self) -> L.RenderOpts:
+    def c(self, n_strokes: int | None = None) -> L.RenderOpts:
+        """The C options; with n_strokes, also checks the coupling's size
+        (the library reads 3 coefficients per stroke)."""
         tm = 0.7 / self.width if self.tau_min is None else self.tau_min
+        cp = self.coupling
+        if cp is not None and not (cp.is_cuda and cp.dtype == torch.float32 and cp.is_contiguous()):
+            raise ValueError("coupling must be a contiguous float32 CUDA tensor [N, 3]")
+        if cp is not None and n_strokes is not None and cp.numel() != 3 * n_strokes:
+            raise ValueError(f"coupling has {cp.numel()} values, expected 3 x {n_strokes}")
         return L.RenderOpts(int(self.width), int(self.height), float(self.tau), float(tm),
                             float(self.tau_c), float(self.eps), int(self.ckpt),
-                            int(self.side_slots))
+                            int(self.side_slots),
+                            L.TBR_TRANSPORT_CAPSULE if cp is None else L.TBR_TRANSPORT_COUPLED,
+                            None if cp is None else cp.data_ptr())
 
     @property
     def pixels(self) -> int:
         return self.width * self.height
+
+
+def check_coupling(coupling) -> float:
+    """Exact positivity check of per-stroke profile coefficients [N, 3]
+    (tbr_coupling_check, on a host copy); returns the smallest g and raises
+    TbrError when a profile is not positive."""
+    c = np.ascontiguousarray(torch.as_tensor(coupling).detach().cpu().numpy(), dtype=np.float32)
+    c = c.reshape(-1, 3)
+    m = C.c_float(0.0)
+    L.check(L.load().tbr_coupling_check(c.ctypes.data_as(C.c_void_p), len(c), C.byref(m)))
+    return m.value
 
 
 def _stream() -> int:
@@ -104,7 +127,7 @@ def render(prog: dict, opts: Opts, mode: str = "soft", tape: bool = False,
     dev = prog["cx"].device
     H, W = opts.height, opts.width
     while True:
-        co = opts.c()
+        co = opts.c(cp.n_strokes)
         nbytes = lib.tbr_render_workspace_bytes(C.byref(co), cp.n_strokes, flags, int(tape))
         ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
         rgb = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
@@ -136,7 +159,7 @@ def render_backward(prog: dict, tape: Tape, grad_rgb: torch.Tensor) -> dict:
     array (same shapes as the program)."""
     lib = L.load()
     cp = c_program(prog)
-    co = tape.opts.c()
+    co = tape.opts.c(cp.n_strokes)
     g = grad_rgb.to(torch.float32).contiguous()
     if g.numel() != 3 * tape.opts.pixels or not g.is_cuda:
         raise ValueError("grad_rgb must be a CUDA tensor of H*W*3 values")
@@ -224,7 +247,7 @@ class FitState:
 
     def _alloc(self):
         lib = L.load()
-        co = self.opts.c()
+        co = self.opts.c(self.n)
         self.nbytes = lib.tbr_fit_workspace_bytes(C.byref(co), self.n, self.k)
         self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.params.device)
 
@@ -234,21 +257,21 @@ class FitState:
     def step(self, target: torch.Tensor) -> torch.Tensor:
         """One fit step; returns the device loss (before the update)."""
         lib = L.load()
-        self.step_index += 1
         a = self.adam
         ao = L.AdamOpts(a.lr_centre, a.lr_angle, a.lr_length, a.lr_width, a.lr_logits,
                         a.lr_palette, a.beta1, a.beta2, a.eps, a.r_lo, a.r_hi, a.l_max,
-                        self.step_index)
-        co = self.opts.c()
+                        self.step_index + 1)
+        co = self.opts.c(self.n)
         t = target.to(torch.float32).contiguous()
         L.check(lib.tbr_fit_step(self.n, self.k, _ptr(self.params), _ptr(self.grads),
                                  _ptr(self.m), _ptr(self.v), C.byref(ao), C.byref(co), _ptr(t),
                                  _ptr(self.loss), _ptr(self.ws), self.nbytes, _stream()))
+        self.step_index += 1  # counted only once the library has taken the step
         return self.loss
 
     def _records(self):
         lib = L.load()
-        co = self.opts.c()
+        co = self.opts.c(self.n)
         mr = C.c_int32(0)
         st = lib.tbr_tape_records(_ptr(self.ws), self.nbytes, C.byref(co), self.n, C.byref(mr),
                                   _stream())
@@ -292,7 +315,7 @@ class MultiFit:
         for j, f in enumerate(self.states):
             a = f.adam
             arr[j] = L.FitJob(f.n, f.k, _ptr(f.params), _ptr(f.grads), _ptr(f.m), _ptr(f.v),
-                              _ptr(f._target), _ptr(f.loss), f.opts.c(),
+                              _ptr(f._target), _ptr(f.loss), f.opts.c(f.n),
                               L.AdamOpts(a.lr_centre, a.lr_angle, a.lr_length, a.lr_width,
                                          a.lr_logits, a.lr_palette, a.beta1, a.beta2, a.eps,
                                          a.r_lo, a.r_hi, a.l_max, max(f.step_index, 1)))
@@ -312,8 +335,13 @@ class MultiFit:
             f._target = t.to(torch.float32).contiguous()
             f.step_index += 1
         jobs = self._jobs()
-        L.check(lib.tbr_fit_multi_step(jobs, len(self.states), _ptr(self.ws), self.nbytes,
-                                       _stream()))
+        try:
+            L.check(lib.tbr_fit_multi_step(jobs, len(self.states), _ptr(self.ws), self.nbytes,
+                                           _stream()))
+        except L.TbrError:
+            for f in self.states:  # the library rejected the step: nothing was updated
+                f.step_index -= 1
+            raise
         return [f.loss for f in self.states]
 
     def tape_records(self) -> list:

@@ -69,9 +69,12 @@ int n_ckpt(const tbr_render_opts* o, int n) {
   return 1 + (n - 1) / o->ckpt_interval;
 }
 
-// Render workspace: [recs][status][tape: nrec | ckpt | side_idx | side_xy]
+bool coupled(const tbr_render_opts* o) { return o->transport == TBR_TRANSPORT_COUPLED; }
+
+// Render workspace: [recs][status][coup][tape: nrec | ckpt | side_idx | side_xy]
+// (coup: the strokes' profile cubics, coupled transport only)
 struct RenderLayout {
-  size_t recs, status, nrec, ckpt_xy, ckpt_t, side_idx, side_xy, total;
+  size_t recs, status, coup, nrec, ckpt_xy, ckpt_t, side_idx, side_xy, total;
 };
 
 RenderLayout render_layout(const tbr_render_opts* o, int n, bool tape) {
@@ -81,6 +84,10 @@ RenderLayout render_layout(const tbr_render_opts* o, int n, bool tape) {
   off = align_up(off + (size_t)(n > 0 ? n : 1) * sizeof(StrokeRec));
   L.status = off;
   off = align_up(off + 64);
+  if (coupled(o)) {
+    L.coup = off;
+    off = align_up(off + (size_t)(n > 0 ? n : 1) * sizeof(float4));
+  }
   if (tape) {
     size_t P = n_pixels(o);
     L.nrec = off;
@@ -158,6 +165,11 @@ tbr_status check_opts(const tbr_render_opts* o, bool soft, bool tape) {
   if (o->ckpt_interval < 0) return fail(TBR_E_INVALID, "ckpt_interval must be >= 0");
   if (tape && o->side_slots < 1) return fail(TBR_E_INVALID, "side_slots must be >= 1 with a tape");
   if (o->side_slots < 0) return fail(TBR_E_INVALID, "side_slots must be >= 0");
+  if (o->transport != TBR_TRANSPORT_CAPSULE && o->transport != TBR_TRANSPORT_COUPLED)
+    return fail(TBR_E_INVALID, "transport %d is not TBR_TRANSPORT_CAPSULE or _COUPLED",
+                o->transport);
+  if (coupled(o) && !o->coupling)
+    return fail(TBR_E_INVALID, "the coupled transport needs the coupling coefficients");
   return TBR_OK;
 }
 
@@ -176,7 +188,13 @@ KProgram kprog(const tbr_program* p) {
   return KProgram{p->n_strokes, p->n_palette, p->cx, p->cy, p->angle, p->length,
                   p->half_width, p->logits, p->palette};
 }
-KOpts kopts(const tbr_render_opts* o) { return KOpts{o->tau, o->tau_min, o->tau_c, o->eps_floor}; }
+KOpts kopts(const tbr_render_opts* o) {
+  return KOpts{o->tau, o->tau_min, o->tau_c, o->eps_floor, coupled(o) ? o->coupling : nullptr};
+}
+
+float4* coup_of(char* ws, const RenderLayout& L, const tbr_render_opts* o) {
+  return coupled(o) ? reinterpret_cast<float4*>(ws + L.coup) : nullptr;
+}
 
 KTape ktape(char* ws, const RenderLayout& L, const tbr_render_opts* o, bool tape) {
   KTape t{};
@@ -194,10 +212,10 @@ KTape ktape(char* ws, const RenderLayout& L, const tbr_render_opts* o, bool tape
 }
 
 tbr_status launch_prep(const tbr_program* p, const tbr_render_opts* o, StrokeRec* recs,
-                       int32_t* status, hipStream_t st) {
+                       int32_t* status, float4* coup, hipStream_t st) {
   int nb = (p->n_strokes + 255) / 256;
   if (nb < 1) nb = 1;
-  k_stroke_prep<<<nb, 256, 0, st>>>(kprog(p), kopts(o), recs, status);
+  k_stroke_prep<<<nb, 256, 0, st>>>(kprog(p), kopts(o), recs, status, coup);
   return check_launch("stroke_prep");
 }
 
@@ -226,13 +244,17 @@ tbr_status launch_reduce(const tbr_program* p, const tbr_render_opts* o, const t
 
 // The fused fit kernel over the jobs' (job, tile) items; the cursor is
 // cleared by a fill kernel (no memset node if the caller captures a graph).
-tbr_status launch_fused(const FitJobsK& K, int* cursor, hipStream_t st) {
+tbr_status launch_fused(const FitJobsK& K, int* cursor, bool coup, hipStream_t st) {
   k_fill_i32<<<1, 64, 0, st>>>(cursor, 1, 0);
   tbr_status s = check_launch("fill");
   if (s) return s;
   {
     Timed tm("fit_fused", st);
-    k_fit_fused<<<std::min(K.n_items, 256 * 8), 256, 0, st>>>(K, cursor);
+    const int grid = std::min(K.n_items, 256 * 8);
+    if (coup)
+      k_fit_fused<true><<<grid, 256, 0, st>>>(K, cursor);
+    else
+      k_fit_fused<false><<<grid, 256, 0, st>>>(K, cursor);
   }
   return check_launch("fit_fused");
 }
@@ -244,10 +266,16 @@ tbr_status launch_backward(const tbr_program* p, const tbr_render_opts* o, const
   KTape t = ktape(const_cast<char*>(tape_ws), RL, o, true);
   float* partial = reinterpret_cast<float*>(ws + BL.partial);
   const StrokeRec* recs = reinterpret_cast<const StrokeRec*>(tape_ws + RL.recs);
+  const float4* coup = coup_of(const_cast<char*>(tape_ws), RL, o);
   dim3 grid(tiles_x(o), tiles_y(o));
   {
     Timed tm("replay", st);
-    k_replay<<<grid, 256, 0, st>>>(recs, n, o->width, o->height, p->palette, grad_rgb, t, partial);
+    if (coup)
+      k_replay<true><<<grid, 256, 0, st>>>(recs, coup, n, o->width, o->height, p->palette,
+                                           grad_rgb, t, partial);
+    else
+      k_replay<false><<<grid, 256, 0, st>>>(recs, nullptr, n, o->width, o->height, p->palette,
+                                            grad_rgb, t, partial);
   }
   tbr_status s = check_launch("replay");
   if (s) return s;
@@ -322,7 +350,8 @@ tbr_status fit_core(int32_t n_strokes, int32_t n_palette, float* params, float* 
                       g + 5 * N + (size_t)N * K};
   StrokeRec* recs = reinterpret_cast<StrokeRec*>(rws + FL.r.recs);
   KTape t = ktape(rws, FL.r, opts, true);
-  if ((s = launch_prep(&prog, opts, recs, t.status, st))) return s;
+  float4* coup = coup_of(rws, FL.r, opts);
+  if ((s = launch_prep(&prog, opts, recs, t.status, coup, st))) return s;
   float* lpart = reinterpret_cast<float*>(ws + FL.loss_part);
   // soft forward with tape, L2 seed and replay adjoint of each tile in one
   // persistent launch (one drain of the GPU per step instead of two)
@@ -330,6 +359,7 @@ tbr_status fit_core(int32_t n_strokes, int32_t n_palette, float* params, float* 
   KJ.n_jobs = 1;
   FitJobK& D = KJ.job[0];
   D.recs = recs;
+  D.coup = coup;
   D.palette = prog.palette;
   D.target = target_rgb;
   D.partial = reinterpret_cast<float*>(bws + FL.b.partial);
@@ -341,7 +371,8 @@ tbr_status fit_core(int32_t n_strokes, int32_t n_palette, float* params, float* 
   D.tiles_x = tiles_x(opts);
   D.item0 = 0;
   KJ.n_items = (int)n_tiles(opts);
-  if ((s = launch_fused(KJ, reinterpret_cast<int*>(ws + FL.cursor), st))) return s;
+  if ((s = launch_fused(KJ, reinterpret_cast<int*>(ws + FL.cursor), coup != nullptr, st)))
+    return s;
   k_loss_final<<<1, 256, 0, st>>>(lpart, (int)n_tiles(opts), 1.0f / (3.0f * (float)n_pixels(opts)),
                                   loss);
   if ((s = check_launch("loss_final"))) return s;
@@ -379,21 +410,32 @@ tbr_status tbr_render(const tbr_program* prog, const tbr_render_opts* opts, int3
   char* ws = static_cast<char*>(workspace);
   StrokeRec* recs = reinterpret_cast<StrokeRec*>(ws + L.recs);
   KTape t = ktape(ws, L, opts, with_tape != 0);
-  if ((s = launch_prep(prog, opts, recs, t.status, st))) return s;
+  float4* coup = coup_of(ws, L, opts);
+  if ((s = launch_prep(prog, opts, recs, t.status, coup, st))) return s;
   dim3 grid(tiles_x(opts), tiles_y(opts));
+  const int n = prog->n_strokes, W = opts->width, H = opts->height;
   if (soft) {
     {
       Timed tm("trace_soft", st);
-      k_trace_soft<<<grid, 256, 0, st>>>(recs, prog->n_strokes, opts->width, opts->height,
-                                         prog->palette, rgb, t, KSeed{nullptr, nullptr, nullptr});
+      const KSeed none{nullptr, nullptr, nullptr};
+      if (coup)
+        k_trace_soft<true><<<grid, 256, 0, st>>>(recs, coup, n, W, H, prog->palette, rgb, t, none);
+      else
+        k_trace_soft<false><<<grid, 256, 0, st>>>(recs, nullptr, n, W, H, prog->palette, rgb, t,
+                                                  none);
     }
     if ((s = check_launch("trace_soft"))) return s;
   }
   if (hard && (label || owner || (!soft && rgb))) {
     {
       Timed tm("trace_hard", st);
-      k_trace_hard<<<grid, 256, 0, st>>>(recs, prog->n_strokes, opts->width, opts->height,
-                                         prog->palette, soft ? nullptr : rgb, label, owner);
+      float* hrgb = soft ? nullptr : rgb;
+      if (coup)
+        k_trace_hard<true><<<grid, 256, 0, st>>>(recs, coup, n, W, H, prog->palette, hrgb, label,
+                                                 owner);
+      else
+        k_trace_hard<false><<<grid, 256, 0, st>>>(recs, nullptr, n, W, H, prog->palette, hrgb,
+                                                  label, owner);
     }
     if ((s = check_launch("trace_hard"))) return s;
   }
@@ -520,6 +562,49 @@ tbr_status tbr_fit_loop_step(int32_t n_strokes, int32_t n_palette, float* theta,
   return check_launch("window_adam");
 }
 
+tbr_status tbr_coupling_check(const float* coupling, int32_t n_strokes, float* min_g) {
+  if (!coupling || n_strokes < 0) return fail(TBR_E_INVALID, "null argument");
+  // g in W = cos(4 pi v) is the cubic a0 + a1 W + a2 W^2 + a3 W^3 on [-1, 1]:
+  // its minimum is at an end or at a real root of g'(W) inside.
+  double worst = INFINITY;
+  int32_t bad = -1;
+  for (int32_t i = 0; i < n_strokes; ++i) {
+    const double c1 = coupling[3 * i], c2 = coupling[3 * i + 1], c3 = coupling[3 * i + 2];
+    if (!std::isfinite(c1) || !std::isfinite(c2) || !std::isfinite(c3)) {
+      worst = -INFINITY;
+      bad = i;
+      break;
+    }
+    const double a0 = 1.0 - c2, a1 = c1 - 3.0 * c3, a2 = 2.0 * c2, a3 = 4.0 * c3;
+    auto g = [&](double W) { return a0 + W * (a1 + W * (a2 + W * a3)); };
+    double m = std::min(g(-1.0), g(1.0));
+    // g'(W) = a1 + 2 a2 W + 3 a3 W^2
+    double roots[2];
+    int nr = 0;
+    if (a3 != 0.0) {
+      const double A = 3.0 * a3, B = 2.0 * a2, D = B * B - 4.0 * A * a1;
+      if (D >= 0.0) {
+        const double q = -0.5 * (B + std::copysign(std::sqrt(D), B));
+        if (q != 0.0) roots[nr++] = q / A;
+        if (q != 0.0) roots[nr++] = a1 / q;
+        else roots[nr++] = 0.0;  // B = D = 0: a double root at 0
+      }
+    } else if (a2 != 0.0) {
+      roots[nr++] = -a1 / (2.0 * a2);
+    }
+    for (int k = 0; k < nr; ++k)
+      if (roots[k] > -1.0 && roots[k] < 1.0) m = std::min(m, g(roots[k]));
+    if (m < worst) {
+      worst = m;
+      bad = i;
+    }
+  }
+  if (min_g) *min_g = n_strokes > 0 ? (float)worst : 1.0f;
+  if (n_strokes > 0 && !(worst > 0.0))
+    return fail(TBR_E_INVALID, "profile of stroke %d is not positive (min g = %g)", bad, worst);
+  return TBR_OK;
+}
+
 void tbr_schedule_at(int32_t step, int32_t total_steps, float tau_first, float tau_last,
                      float tau_c_first, float tau_c_last, float* tau, float* tau_c,
                      float* lr_scale) {
@@ -553,6 +638,8 @@ tbr_status tbr_fit_multi_step(const tbr_fit_job* jobs, int32_t n_jobs, void* wor
       return fail(TBR_E_INVALID, "job %d: null argument", j);
     if ((s = check_opts(&J.opts, true, true))) return s;
     if ((s = check_adam(&J.adam))) return s;
+    if (J.opts.transport != jobs[0].opts.transport)
+      return fail(TBR_E_INVALID, "job %d: every job of one step must use the same transport", j);
   }
   const size_t need = multi_offset(jobs, n_jobs);
   if (workspace_bytes < need)
@@ -589,9 +676,11 @@ tbr_status tbr_fit_multi_step(const tbr_fit_job* jobs, int32_t n_jobs, void* wor
                                  g + 5 * N + (size_t)N * Kp};
     StrokeRec* recs = reinterpret_cast<StrokeRec*>(rws + FL.r.recs);
     KTape t = ktape(rws, FL.r, &J.opts, true);
-    if ((s = launch_prep(&progs[j], &J.opts, recs, t.status, st))) return s;
+    float4* coup = coup_of(rws, FL.r, &J.opts);
+    if ((s = launch_prep(&progs[j], &J.opts, recs, t.status, coup, st))) return s;
     FitJobK& D = K.job[q];
     D.recs = recs;
+    D.coup = coup;
     D.palette = progs[j].palette;
     D.target = J.target_rgb;
     D.partial = reinterpret_cast<float*>(base + FL.base_b + FL.b.partial);
@@ -605,7 +694,7 @@ tbr_status tbr_fit_multi_step(const tbr_fit_job* jobs, int32_t n_jobs, void* wor
     items += (int)n_tiles(&J.opts);
   }
   K.n_items = items;
-  if ((s = launch_fused(K, reinterpret_cast<int*>(ws), st))) return s;
+  if ((s = launch_fused(K, reinterpret_cast<int*>(ws), coupled(&jobs[0].opts), st))) return s;
   for (int j = 0; j < n_jobs; ++j) {
     const tbr_fit_job& J = jobs[j];
     const FitLayout& FL = layouts[j];

@@ -8,6 +8,8 @@
 //   fraction w (Prop. centred arclength), the backward root (Eq. back) with
 //   the implemented floor C >= (eps r)^2 (Sec. 5.2), the forward root
 //   (Eq. fwd), and the soft coverage of Eq. (relax) clamped at 1 - 1e-7.
+//   The calibrated variant (Eq. coupling, Eq. profile) changes only the area
+//   a leaf receives, and with it where the leaf's deposit ends (Leaf).
 //
 // Transcendentals: raw v_sqrt/v_rcp/v_exp (about 1 ulp) plus the
 // first-quadrant atan / sin / cos polynomials of minimax_coeffs.h (Remez
@@ -128,16 +130,6 @@ __device__ __forceinline__ float area_to_dist(float q, const StrokeRec& g) {
   return q * rcp(g.ell + hw_sqrt(fmaf(g.ell, g.ell, kPi * q)));
 }
 
-// Backward numerator C = A(sigma') - A(r), factored (Eq. back).
-__device__ __forceinline__ float back_area(float sig, const StrokeRec& g) {
-  return (sig - g.r) * fmaf(kPi, sig + g.r, g.two_ell);
-}
-
-// Forward numerator B = A(sigma) + A(r) (Eq. fwd).
-__device__ __forceinline__ float fwd_area(float sig, const StrokeRec& g) {
-  return fmaf(sig, fmaf(kPi, sig, g.two_ell), g.ar);
-}
-
 // sin(d) and cos(d) - 1 for d in [-pi/2, pi/2] (odd / even polynomials).
 __device__ __forceinline__ void sincosm1(float d, float& s, float& cm1) {
   float u = d * d;
@@ -168,6 +160,65 @@ __device__ __forceinline__ void sincosm1_small(float d, float& s, float& cm1) {
   cm1 = u * fmaf(u, fmaf(u, -1.f / 720.f, 1.f / 24.f), -0.5f);
 }
 
+// What the stroke inserts along the leaf of a charted point. Uniform
+// insertion (Eq. phi): the area A_l(r) on every leaf, whose deposit ends at
+// distance r. Calibrated coupling (Eq. coupling, Eq. profile): the leaf of
+// centred fraction w receives G = A_l(r) g(w), g(w) = 1 + sum_k c_k
+// cos(4 pi k w), and its deposit ends at the root rl of A_l(rl) = G; Eq.
+// back and Eq. fwd then hold with r replaced by rl.
+struct Leaf {
+  float r;        // edge of the deposit on this leaf
+  float ar;       // area inserted along it, A_l(r) or G
+  float g;        // g(w) (coupled only)
+  float dg;       // dg/dw (coupled only)
+  float inv_per;  // 1 / P_l(rl) (coupled only)
+};
+
+__device__ __forceinline__ Leaf uniform_leaf(const StrokeRec& g) {
+  Leaf lf;
+  lf.r = g.r;
+  lf.ar = g.ar;
+  lf.g = 1.f;
+  lf.dg = 0.f;
+  lf.inv_per = 0.f;
+  return lf;
+}
+
+// a = (a0, a1, a2, a3): g as the cubic a0 + a1 W + a2 W^2 + a3 W^3 in
+// W = cos(4 pi w) (cos 2x = 2 cos^2 x - 1, cos 3x = 4 cos^3 x - 3 cos x:
+// a0 = 1 - c2, a1 = c1 - 3 c3, a2 = 2 c2, a3 = 4 c3). w is folded into
+// [0, 1/4], so 4 pi w - pi/2 lies in the polynomials' range. A profile
+// that is not positive somewhere is invalid input; there g is taken as 0.
+__device__ __forceinline__ Leaf coupled_leaf(float w, const StrokeRec& g, const float4 a) {
+  Leaf lf;
+  float s, cm1;
+  sincosm1(fmaf(2.f * kTwoPi, w, -kHalfPi), s, cm1);
+  const float W = -s;          // cos(4 pi w)
+  const float s4 = 1.f + cm1;  // sin(4 pi w)
+  const float gv = fmaf(fmaf(fmaf(a.w, W, a.z), W, a.y), W, a.x);
+  const float dgw = fmaf(fmaf(3.f * a.w, W, 2.f * a.z), W, a.y);
+  const bool pos = gv > 0.f;
+  lf.g = pos ? gv : 0.f;
+  lf.dg = pos ? -2.f * kTwoPi * s4 * dgw : 0.f;  // dW/dw = -4 pi sin(4 pi w)
+  lf.ar = g.ar * lf.g;
+  // rl = G / (l + sqrt(l^2 + pi G)), and P_l(rl) = 2 sqrt(l^2 + pi G)
+  const float X = fmaf(g.ell, g.ell, kPi * lf.ar);
+  const float rs = X > 0.f ? __builtin_amdgcn_rsqf(X) : 0.f;
+  lf.r = lf.ar > 0.f ? lf.ar * rcp(g.ell + X * rs) : 0.f;
+  lf.inv_per = 0.5f * rs;
+  return lf;
+}
+
+// Backward numerator C = A(sigma') - A(rl), factored (Eq. back).
+__device__ __forceinline__ float back_area(float sig, const Leaf& lf, float two_ell) {
+  return (sig - lf.r) * fmaf(kPi, sig + lf.r, two_ell);
+}
+
+// Forward numerator B = A(sigma) + A(rl) (Eq. fwd).
+__device__ __forceinline__ float fwd_area(float sig, const Leaf& lf, float two_ell) {
+  return fmaf(sig, fmaf(kPi, sig, two_ell), lf.ar);
+}
+
 // One application of the insertion map or its inverse to a charted point,
 // as a DISPLACEMENT in the folded local frame. The new point is the one on
 // the level curve at distance sig_o with the same fraction w. Writing the
@@ -193,14 +244,16 @@ struct Move {
 // satisfies sqrt(l^2 + pi q) = l + pi sig_o, so P_l(sig_o) =
 // 2 sqrt(l^2 + pi q): one reciprocal square root gives both.
 template <bool kPer = false>
-__device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, bool backward) {
+__device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, bool backward,
+                                         const Leaf& lf) {
   Move m;
   const float two_ell = g.two_ell;
   // psi: Eq. (back) with the implemented floor; Phi: Eq. (fwd)
-  float cq = back_area(c.sig, g);
+  float cq = back_area(c.sig, lf, two_ell);
   m.floored = backward && cq < g.floor_c;
-  float q = backward ? fmaxf(cq, g.floor_c) : fwd_area(c.sig, g);
-  float num = backward ? (m.floored ? g.floor_c - c.sig * fmaf(kPi, c.sig, two_ell) : -g.ar) : g.ar;
+  float q = backward ? fmaxf(cq, g.floor_c) : fwd_area(c.sig, lf, two_ell);
+  float num =
+      backward ? (m.floored ? g.floor_c - c.sig * fmaf(kPi, c.sig, two_ell) : -lf.ar) : lf.ar;
   if constexpr (kPer) {
     const float X = fmaf(g.ell, g.ell, kPi * q);
     const float rs = __builtin_amdgcn_rsqf(X);
@@ -249,17 +302,19 @@ __device__ __forceinline__ void advance(double& x, double& y, const Chart& c, co
   step_by(x, y, c.sgs * m.dS, c.sgh * m.dH, g);
 }
 
-// Soft coverage alpha = sigmoid((r - sigma) / wd) with alpha <= 1 - 1e-7,
-// returned with q = 1 - alpha and 1 / q = 1 + e^z (exact identities of the
-// logistic function, so no cancellation in 1 - alpha).
+// Soft coverage alpha = sigmoid((edge - sigma) / wd) with alpha <= 1 - 1e-7
+// (edge = the deposit's edge on the point's leaf, r when uniform; wd =
+// max(tau r, tau_min) of the stroke), returned with q = 1 - alpha and
+// 1 / q = 1 + e^z (exact identities of the logistic function, so no
+// cancellation in 1 - alpha).
 struct Cover {
   float z, alpha, q, inv_q;
   bool clamped;
 };
 
-__device__ __forceinline__ Cover cover(float sig, const StrokeRec& g) {
+__device__ __forceinline__ Cover cover(float sig, const StrokeRec& g, float edge) {
   Cover v;
-  v.z = (g.r - sig) * g.inv_wd;
+  v.z = (edge - sig) * g.inv_wd;
   float ez = hw_exp(v.z);
   v.clamped = !(ez < kEzMax);
   ez = v.clamped ? kEzMax : ez;
@@ -311,9 +366,12 @@ struct VjpOut {
 };
 
 // kCover = false drops the coverage terms (a far stroke, alpha = 0 to FP32).
-template <bool kCover>
+// kCoupled: the leaf's area G = A_l(r) g(w) and edge rl depend on w, l and r
+// (the Leaf of the input point): dG = g P_l(r) dr + 2 r g dl + A_l(r) g' dw
+// and P_l(rl) drl + 2 rl dl = dG.
+template <bool kCover, bool kCoupled = false>
 __device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, float lx,
-                                           float ly, float mu) {
+                                           float ly, float mu, const Leaf& lf) {
   VjpOut o;
   const float two_ell = g.two_ell;
   // out = m + sgs S' e + sgh H' n
@@ -342,8 +400,25 @@ __device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, f
   float p1 = fmaf(kTwoPi, v.sig, two_ell);
   const float pr = g.per_r;
   float sigb = v.floored ? 0.f : cb * p1;
-  o.gr = v.floored ? cb * g.dfloor_dr : -(cb * pr);
-  ellb = v.floored ? ellb : fmaf(2.f * (v.sig - g.r), cb, ellb);
+  if constexpr (kCoupled) {
+    // C = A_l(sigma') - G
+    o.gr = v.floored ? cb * g.dfloor_dr : -(cb * pr * lf.g);
+    ellb = v.floored ? ellb : fmaf(2.f * fmaf(-g.r, lf.g, v.sig), cb, ellb);
+    wb = v.floored ? wb : fmaf(-cb * g.ar, lf.dg, wb);
+    // coverage z = (rl - sigma') / wd, before w's adjoint is passed on
+    if constexpr (kCover) {
+      float zb = v.clamped ? 0.f : mu * v.alpha * v.q;
+      float zw = zb * g.inv_wd;
+      sigb -= zw;
+      float rlb = zw * lf.inv_per;  // adjoint of G through rl
+      o.gr = fmaf(rlb * pr, lf.g, fmaf(-zw * v.z, g.dwd_dr, o.gr));
+      ellb = fmaf(2.f * rlb, fmaf(g.r, lf.g, -lf.r), ellb);
+      wb = fmaf(rlb * g.ar, lf.dg, wb);
+    }
+  } else {
+    o.gr = v.floored ? cb * g.dfloor_dr : -(cb * pr);
+    ellb = v.floored ? ellb : fmaf(2.f * (v.sig - g.r), cb, ellb);
+  }
   // w = t / P_l(sigma')
   float tb = wb * v.inv_p1;
   sigb = fmaf(-kTwoPi * v.w, tb, sigb);
@@ -355,7 +430,7 @@ __device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, f
   float eb = tb * v.cs;
   float hb = -(tb * v.sn);
   // coverage: z = (r - sigma') / wd
-  if constexpr (kCover) {
+  if constexpr (kCover && !kCoupled) {
     float zb = v.clamped ? 0.f : mu * v.alpha * v.q;
     float zw = zb * g.inv_wd;
     sigb -= zw;

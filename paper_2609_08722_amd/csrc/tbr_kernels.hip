@@ -80,11 +80,16 @@ __device__ __forceinline__ StrokeRec prep_stroke(const KProgram& p, const KOpts&
 
 // One thread per stroke of one program.
 __global__ void __launch_bounds__(256)
-    k_stroke_prep(KProgram p, KOpts o, StrokeRec* __restrict__ out, int32_t* __restrict__ status) {
+    k_stroke_prep(KProgram p, KOpts o, StrokeRec* __restrict__ out, int32_t* __restrict__ status,
+                  float4* __restrict__ coup) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0 && status) *status = 0;  // tape record high-water mark of this launch
   if (i >= p.n) return;
   out[i] = prep_stroke(p, o, i);
+  if (coup) {  // Eq. profile as a cubic in cos(4 pi w) (see coupled_leaf)
+    const float c1 = o.coupling[3 * i], c2 = o.coupling[3 * i + 1], c3 = o.coupling[3 * i + 2];
+    coup[i] = make_float4(1.f - c2, fmaf(-3.f, c3, c1), 2.f * c2, 4.f * c3);
+  }
 }
 
 // Every request of a serving tick in one launch: request j owns the blocks
@@ -110,6 +115,22 @@ constexpr float kFarZ = -28.f;
 __device__ __forceinline__ StrokeRec load_rec(const StrokeRec* __restrict__ recs, int i) {
   i = __builtin_amdgcn_readfirstlane(i);
   return recs[i];
+}
+
+// Wave-uniform load of a stroke's profile coefficients (coupled variant).
+__device__ __forceinline__ float4 load_coup(const float4* __restrict__ coup, int i) {
+  i = __builtin_amdgcn_readfirstlane(i);
+  return coup[i];
+}
+
+template <bool kC>
+__device__ __forceinline__ Leaf leaf_at(const Chart& c, const StrokeRec& g,
+                                        const float4* __restrict__ coup, int i) {
+  if constexpr (kC) {
+    return coupled_leaf(c.w, g, load_coup(coup, i));
+  } else {
+    return uniform_leaf(g);
+  }
 }
 
 struct PixelId {
@@ -140,8 +161,9 @@ struct SoftOut {
   int nrec;          // records pushed (floor bound)
 };
 
-template <bool kTape>
-__device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs, int n,
+template <bool kTape, bool kC = false>
+__device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs,
+                                              const float4* __restrict__ coup, int n,
                                               const PixelId& id, int width, int height,
                                               const float* __restrict__ palette,
                                               const KTape& tape) {
@@ -168,13 +190,14 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
       next_ck -= k;
     }
     Chart c = chart(x, y, g);
+    const Leaf lf = leaf_at<kC>(c, g, coup, i);
     // Coverage and compositing, unless the stroke is far from every pixel
     // of the wave: then alpha < 7e-13, 1 - alpha rounds to 1 and T and C
     // are unchanged to FP32 rounding. Lanes past a ragged canvas edge trace
     // a point just outside the canvas and vote too: that can only keep the
     // exact path.
-    if (!wave_all((g.r - c.sig) * g.inv_wd < kFarZ)) {
-      Cover v = cover(c.sig, g);
+    if (!wave_all((lf.r - c.sig) * g.inv_wd < kFarZ)) {
+      Cover v = cover(c.sig, g, lf.r);
       float t = trans_value(tm, te);
       float ta = t * v.alpha;
       cr = fmaf(ta, g.cr, cr);
@@ -184,7 +207,7 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
       renorm(tm, te);
     }
     // backward map with the implemented floor; record where it binds
-    Move mv = displace(c, g, true);
+    Move mv = displace(c, g, true, lf);
     if (mv.floored) {
       if (write_tape && nrec < tape.side_slots) {
         size_t o = (size_t)nrec * P + id.p;
@@ -211,7 +234,9 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
 
 // Hard trace of one pixel per lane: first footprint hit going N -> 1; lanes
 // retire on a hit and the wave leaves the stroke loop once all have retired.
-__device__ __forceinline__ void hard_pixel(const StrokeRec* __restrict__ recs, int n,
+template <bool kC = false>
+__device__ __forceinline__ void hard_pixel(const StrokeRec* __restrict__ recs,
+                                           const float4* __restrict__ coup, int n,
                                            const PixelId& id, int width, int height, int& own,
                                            int& lab) {
   double x = (id.px + 0.5) / (double)width;
@@ -224,24 +249,28 @@ __device__ __forceinline__ void hard_pixel(const StrokeRec* __restrict__ recs, i
     const StrokeRec g = load_rec(recs, i);
     if (!done) {
       Chart c = chart(x, y, g);
-      if (c.sig <= g.r) {  // closed footprint
+      const Leaf lf = leaf_at<kC>(c, g, coup, i);
+      if (c.sig <= lf.r) {  // closed footprint
         done = true;
         own = i;
         lab = g.label;
       } else {
-        advance(x, y, c, displace(c, g, true), g);
+        advance(x, y, c, displace(c, g, true, lf), g);
       }
     }
   }
 }
 
+template <bool kC>
 __global__ void __launch_bounds__(256)
-    k_trace_soft(const StrokeRec* __restrict__ recs, int n, int width, int height,
-                 const float* __restrict__ palette, float* __restrict__ rgb, KTape tape, KSeed seed) {
+    k_trace_soft(const StrokeRec* __restrict__ recs, const float4* __restrict__ coup, int n,
+                 int width, int height, const float* __restrict__ palette, float* __restrict__ rgb,
+                 KTape tape, KSeed seed) {
   PixelId id = pixel_of_tile(blockIdx.x, blockIdx.y, width, height);
   const int P = width * height;
-  SoftOut o = tape.ckpt_xy ? soft_pixel<true>(recs, n, id, width, height, palette, tape)
-                           : soft_pixel<false>(recs, n, id, width, height, palette, tape);
+  SoftOut o = tape.ckpt_xy
+                  ? soft_pixel<true, kC>(recs, coup, n, id, width, height, palette, tape)
+                  : soft_pixel<false, kC>(recs, coup, n, id, width, height, palette, tape);
   if (id.active && rgb) {
     rgb[3 * (size_t)id.p + 0] = o.cr;
     rgb[3 * (size_t)id.p + 1] = o.cg;
@@ -278,13 +307,15 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+template <bool kC>
 __global__ void __launch_bounds__(256)
-    k_trace_hard(const StrokeRec* __restrict__ recs, int n, int width, int height,
-                 const float* __restrict__ palette, float* __restrict__ rgb,
-                 int32_t* __restrict__ label, int32_t* __restrict__ owner) {
+    k_trace_hard(const StrokeRec* __restrict__ recs, const float4* __restrict__ coup, int n,
+                 int width, int height, const float* __restrict__ palette,
+                 float* __restrict__ rgb, int32_t* __restrict__ label,
+                 int32_t* __restrict__ owner) {
   PixelId id = pixel_of_tile(blockIdx.x, blockIdx.y, width, height);
   int own, lab;
-  hard_pixel(recs, n, id, width, height, own, lab);
+  hard_pixel<kC>(recs, coup, n, id, width, height, own, lab);
   if (id.active) {
     if (owner) owner[id.p] = own;
     if (label) label[id.p] = lab;
@@ -319,7 +350,7 @@ __global__ void __launch_bounds__(256)
     PixelId id = pixel_of_tile(tile % d.tiles_x, tile / d.tiles_x, d.width, d.height);
     if (d.soft) {
       KTape none{};
-      SoftOut o = soft_pixel<false>(d.recs, d.n, id, d.width, d.height, d.palette, none);
+      SoftOut o = soft_pixel<false>(d.recs, nullptr, d.n, id, d.width, d.height, d.palette, none);
       if (id.active) {
         d.rgb[3 * (size_t)id.p + 0] = o.cr;
         d.rgb[3 * (size_t)id.p + 1] = o.cg;
@@ -327,7 +358,7 @@ __global__ void __launch_bounds__(256)
       }
     } else {
       int own, lab;
-      hard_pixel(d.recs, d.n, id, d.width, d.height, own, lab);
+      hard_pixel(d.recs, nullptr, d.n, id, d.width, d.height, own, lab);
       if (id.active) {
         if (d.owner) d.owner[id.p] = own;
         if (d.label) d.label[id.p] = lab;
@@ -434,7 +465,9 @@ using ReduceLds = float[2][16][kChunk + 1][8];
 // The replay of one 16x16 tile by the whole block (all 256 threads must
 // call it). lcr, lcg, lcb: this lane's dL/dR; prow: the tile's partial row
 // [n + 1][8] (row n = background colour gradient).
-__device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, int n,
+template <bool kC = false>
+__device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
+                                            const float4* __restrict__ coup, int n,
                                             const PixelId& id, int width, int height,
                                             const float* __restrict__ palette, float lcr,
                                             float lcg, float lcb, const KTape& tape,
@@ -494,7 +527,8 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, 
       if (!ck && !wave_any(pop)) {
         // Common case: every lane regenerates x_i = Phi_i(x_{i-1}) (Eq. rpos).
         Chart ca = chart(x, y, g);
-        Move mv = displace<true>(ca, g, false);
+        const Leaf lf = leaf_at<kC>(ca, g, coup, i);
+        Move mv = displace<true>(ca, g, false, lf);
         // unfolded displacement; the new point's signed coordinates are the
         // chart's plus it (sgs (S + dS) = s + sgs dS, exactly)
         const float da = ca.sgs * mv.dS, db = ca.sgh * mv.dH;
@@ -517,19 +551,19 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, 
         vi.sn_o = ca.sn;
         vi.cs_o = ca.cs;
         step_by(x, y, da, db, g);
-        if (wave_all((g.r - vi.sig) * g.inv_wd < kFarZ)) {
+        if (wave_all((lf.r - vi.sig) * g.inv_wd < kFarZ)) {
           // far stroke: alpha, mu dalpha and the colour terms vanish to FP32
           vi.z = 0.f;
           vi.alpha = 0.f;
           vi.q = 1.f;
           vi.clamped = true;
-          VjpOut vo = vjp_step<false>(vi, g, lx, ly, 0.f);
+          VjpOut vo = vjp_step<false, kC>(vi, g, lx, ly, 0.f, lf);
           lx = vo.gx;
           ly = vo.gy;
           float v[5] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr};
           tot = row_sums5(v, lane);
         } else {
-          Cover cv = cover(vi.sig, g);
+          Cover cv = cover(vi.sig, g, lf.r);
           vi.z = cv.z;
           vi.alpha = cv.alpha;
           vi.q = cv.q;
@@ -541,7 +575,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, 
           float mu = t * (lc - lt);
           float ta = t * cv.alpha;
           lt = fmaf(cv.q, lt, cv.alpha * lc);
-          VjpOut vo = vjp_step<true>(vi, g, lx, ly, mu);
+          VjpOut vo = vjp_step<true, kC>(vi, g, lx, ly, mu, lf);
           lx = vo.gx;
           ly = vo.gy;
           float v[8] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
@@ -571,7 +605,8 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, 
         // for a loaded lane the chart is at x_i and psi_i gives the
         // (discarded) x_{i-1}, whose geometry the adjoint needs.
         Chart ca = chart(ax, ay, g);
-        Move mv = displace<true>(ca, g, loaded);
+        const Leaf lf = leaf_at<kC>(ca, g, coup, i);
+        Move mv = displace<true>(ca, g, loaded, lf);
         const float da = ca.sgs * mv.dS, db = ca.sgh * mv.dH;
         const float sn_pt = ca.s + da, hn_pt = ca.h + db;  // signed coordinates of the new point
         VjpIn vi;
@@ -611,7 +646,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, 
           vi.cs_o = ca.cs;
           step_by(x, y, da, db, g);
         }
-        Cover cv = cover(vi.sig, g);
+        Cover cv = cover(vi.sig, g, lf.r);
         vi.z = cv.z;
         vi.alpha = cv.alpha;
         vi.q = cv.q;
@@ -628,7 +663,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, 
         float mu = t * (lc - lt);
         float ta = t * cv.alpha;
         lt = fmaf(cv.q, lt, cv.alpha * lc);
-        VjpOut vo = vjp_step<true>(vi, g, lx, ly, mu);
+        VjpOut vo = vjp_step<true, kC>(vi, g, lx, ly, mu, lf);
         lx = vo.gx;
         ly = vo.gy;
         float v[8] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
@@ -650,10 +685,11 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs, 
 }
 
 
+template <bool kC>
 __global__ void __launch_bounds__(256)
-    k_replay(const StrokeRec* __restrict__ recs, int n, int width, int height,
-             const float* __restrict__ palette, const float* __restrict__ grad_rgb, KTape tape,
-             float* __restrict__ partial) {
+    k_replay(const StrokeRec* __restrict__ recs, const float4* __restrict__ coup, int n,
+             int width, int height, const float* __restrict__ palette,
+             const float* __restrict__ grad_rgb, KTape tape, float* __restrict__ partial) {
   __shared__ ReduceLds lds;
   PixelId id = pixel_of_tile(blockIdx.x, blockIdx.y, width, height);
   const int tile = blockIdx.y * gridDim.x + blockIdx.x;
@@ -663,8 +699,8 @@ __global__ void __launch_bounds__(256)
     lcg = grad_rgb[3 * (size_t)id.p + 1];
     lcb = grad_rgb[3 * (size_t)id.p + 2];
   }
-  replay_tile(recs, n, id, width, height, palette, lcr, lcg, lcb, tape,
-              partial + (size_t)tile * (n + 1) * 8, lds);
+  replay_tile<kC>(recs, coup, n, id, width, height, palette, lcr, lcg, lcb, tape,
+                  partial + (size_t)tile * (n + 1) * 8, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -678,6 +714,7 @@ __global__ void __launch_bounds__(256)
 // The forward and the replay share one register allocation here; asking for
 // 5 waves per SIMD (96 VGPRs, instead of 111 at 4 waves) spills only values
 // that live across a tile or a 16-stroke chunk, never inside a stroke loop.
+template <bool kC>
 __global__ void __launch_bounds__(256, 5) k_fit_fused(FitJobsK jobs, int* __restrict__ cursor) {
   __shared__ ReduceLds lds;
   __shared__ float red[256];
@@ -694,7 +731,8 @@ __global__ void __launch_bounds__(256, 5) k_fit_fused(FitJobsK jobs, int* __rest
     const int tile = it - J.item0;
     PixelId id = pixel_of_tile(tile % J.tiles_x, tile / J.tiles_x, J.width, J.height);
     const int P = J.width * J.height;
-    SoftOut o = soft_pixel<true>(J.recs, J.n, id, J.width, J.height, J.palette, J.tape);
+    SoftOut o = soft_pixel<true, kC>(J.recs, J.coup, J.n, id, J.width, J.height, J.palette,
+                                     J.tape);
     float lcr = 0.f, lcg = 0.f, lcb = 0.f, sq = 0.f;
     if (id.active) {
       float dr = o.cr - J.target[3 * (size_t)id.p + 0];
@@ -716,8 +754,8 @@ __global__ void __launch_bounds__(256, 5) k_fit_fused(FitJobsK jobs, int* __rest
       __syncthreads();
     }
     if (threadIdx.x == 0) J.loss_part[tile] = red[0];
-    replay_tile(J.recs, J.n, id, J.width, J.height, J.palette, lcr, lcg, lcb, J.tape,
-                J.partial + (size_t)tile * (J.n + 1) * 8, lds);
+    replay_tile<kC>(J.recs, J.coup, J.n, id, J.width, J.height, J.palette, lcr, lcg, lcb,
+                    J.tape, J.partial + (size_t)tile * (J.n + 1) * 8, lds);
   }
 }
 
@@ -755,8 +793,9 @@ __global__ void __launch_bounds__(256)
   grad.cx[i] = (float)s[0];
   grad.cy[i] = (float)s[1];
   // a drop's map and coverage are invariant under rotation about its centre:
-  // the angle gradient is exactly zero there (the sum above is rounding noise)
-  grad.angle[i] = p.length[i] == 0.f ? 0.f : (float)s[2];
+  // the angle gradient is exactly zero there (the sum above is rounding
+  // noise). Not so under the coupling, whose profile turns with the stroke.
+  grad.angle[i] = (p.length[i] == 0.f && !o.coupling) ? 0.f : (float)s[2];
   grad.length[i] = p.length[i] < 0.f ? -(float)s[3] : (float)s[3];  // d|L|/dL, +1 at 0
   grad.half_width[i] = (float)s[4];
   // colour weights s_ik = softmax(z_i / tau_c)_k (one-hot argmax when tau_c = 0)
@@ -999,4 +1038,20 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+}  // namespace tbr
+
+namespace tbr {
+// Both variants of the per-pixel kernels: the uniform insertion and the
+// calibrated coupling.
+#define TBR_INSTANTIATE(C)                                                                      \
+  template __global__ void k_trace_soft<C>(const StrokeRec*, const float4*, int, int, int,      \
+                                           const float*, float*, KTape, KSeed);                 \
+  template __global__ void k_trace_hard<C>(const StrokeRec*, const float4*, int, int, int,      \
+                                           const float*, float*, int32_t*, int32_t*);           \
+  template __global__ void k_replay<C>(const StrokeRec*, const float4*, int, int, int,          \
+                                       const float*, const float*, KTape, float*);              \
+  template __global__ void k_fit_fused<C>(FitJobsK, int*);
+TBR_INSTANTIATE(false)
+TBR_INSTANTIATE(true)
+#undef TBR_INSTANTIATE
 }  // namespace tbr

@@ -15,6 +15,7 @@ struct KProgram {
 
 struct KOpts {
   float tau, tau_min, tau_c, eps;
+  const float* coupling;  // [N][3] c_1..c_3 of the calibrated coupling, or null (uniform)
 };
 
 // Replay tape (all device memory, pixel-minor so a wave's accesses coalesce).
@@ -64,6 +65,7 @@ struct ServePrep {
 // One job of the fused multi-job fit (passed by value in the kernel arguments).
 struct FitJobK {
   const StrokeRec* recs;
+  const float4* coup;   // profile cubics (coupled launches only)
   const float* palette;
   const float* target;  // [P*3]
   float* partial;       // [tiles][n + 1][8]
@@ -91,17 +93,22 @@ struct KWindow {
   float lambda_length, lambda_area;
 };
 
-__global__ void k_stroke_prep(KProgram p, KOpts o, StrokeRec* out, int32_t* status);
+__global__ void k_stroke_prep(KProgram p, KOpts o, StrokeRec* out, int32_t* status, float4* coup);
 __global__ void k_window_map(const float* th, float* nat, int n, int kpal, KWindow w);
 __global__ void k_reg_loss(const float* nat, int n, KWindow w, float* loss);
 __global__ void k_window_adam(float* th, const float* g_nat, float* m, float* v, int n, int kpal,
                               KWindow w, KAdam a, const int32_t* records, int capacity);
-__global__ void k_trace_soft(const StrokeRec* recs, int n, int width, int height,
-                             const float* palette, float* rgb, KTape tape, KSeed seed);
-__global__ void k_trace_hard(const StrokeRec* recs, int n, int width, int height,
-                             const float* palette, float* rgb, int32_t* label, int32_t* owner);
-__global__ void k_replay(const StrokeRec* recs, int n, int width, int height, const float* palette,
-                         const float* grad_rgb, KTape tape, float* partial);
+// kC: calibrated coupling (coup = per-stroke profile cubics), else uniform.
+template <bool kC>
+__global__ void k_trace_soft(const StrokeRec* recs, const float4* coup, int n, int width,
+                             int height, const float* palette, float* rgb, KTape tape, KSeed seed);
+template <bool kC>
+__global__ void k_trace_hard(const StrokeRec* recs, const float4* coup, int n, int width,
+                             int height, const float* palette, float* rgb, int32_t* label,
+                             int32_t* owner);
+template <bool kC>
+__global__ void k_replay(const StrokeRec* recs, const float4* coup, int n, int width, int height,
+                         const float* palette, const float* grad_rgb, KTape tape, float* partial);
 __global__ void k_sum_tiles(const float* partial, int rows8, int n_tiles, int tiles_per_group,
                             double* out);
 __global__ void k_finalize(const double* groups, int n_groups, KProgram p, KOpts o, KGrad grad,
@@ -111,6 +118,7 @@ __global__ void k_palette_grad(const float* pal_terms, int n, int kpal, const fl
 __global__ void k_loss_final(const float* part, int n_part, float inv_count, float* loss);
 __global__ void k_adam(float* prm, const float* grd, float* m, float* v, int n, int kpal, KAdam a,
                        const int32_t* records, int capacity);
+template <bool kC>
 __global__ void k_fit_fused(FitJobsK jobs, int* cursor);
 __global__ void k_serve(const ServeDesc* descs, const uint2* items, int n_items, int* cursor);
 __global__ void k_serve_prep(const ServePrep* preps, int n_req);

@@ -72,16 +72,17 @@ def window_map(theta: torch.Tensor, n: int, k: int, window: Window) -> torch.Ten
 
 class FitLoop:
     """Device state of a fit: free parameters theta, Adam moments, and the
-    program, gradient and loss of the last step."""
+    program, gradient and loss of the last step. coupling: [N, 3] profile
+    coefficients of the calibrated transport, or None (capsule)."""
 
     def __init__(self, theta: torch.Tensor, n: int, k: int, width: int, height: int,
                  window: Window | None = None, schedule: Schedule | None = None,
-                 ckpt: int = 256, side_slots: int = 16):
+                 ckpt: int = 256, side_slots: int = 16, coupling: torch.Tensor | None = None):
         self.theta = theta.to(torch.float32).contiguous().clone()
         self.n, self.k = n, k
         self.window = window or Window()
         self.schedule = schedule or Schedule()
-        self.opts = Opts(width, height, ckpt=ckpt, side_slots=side_slots)
+        self.opts = Opts(width, height, ckpt=ckpt, side_slots=side_slots, coupling=coupling)
         self.params = torch.empty_like(self.theta)
         self.grads = torch.zeros_like(self.theta)
         self.m = torch.zeros_like(self.theta)
@@ -92,7 +93,7 @@ class FitLoop:
 
     def _alloc(self):
         lib = L.load()
-        self.nbytes = lib.tbr_fit_workspace_bytes(C.byref(self.opts.c()), self.n, self.k)
+        self.nbytes = lib.tbr_fit_workspace_bytes(C.byref(self.opts.c(self.n)), self.n, self.k)
         self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.theta.device)
 
     def step(self, target: torch.Tensor) -> torch.Tensor:
@@ -102,23 +103,23 @@ class FitLoop:
         s = self.schedule
         tau, tau_c, lr = s.at(self.step_index)
         self.opts.tau, self.opts.tau_c = tau, tau_c
-        self.step_index += 1
         a = Adam()
         ao = L.AdamOpts(s.lr_anchor * lr, 0.0, s.lr_offset * lr, s.lr_width * lr,
                         s.lr_colour * lr, s.lr_palette * lr, a.beta1, a.beta2, a.eps,
-                        a.r_lo, a.r_hi, a.l_max, self.step_index)
+                        a.r_lo, a.r_hi, a.l_max, self.step_index + 1)
         w = self.window.c()
         t = target.to(torch.float32).contiguous()
         L.check(lib.tbr_fit_loop_step(self.n, self.k, _ptr(self.theta), _ptr(self.params),
                                       _ptr(self.grads), _ptr(self.m), _ptr(self.v), C.byref(w),
-                                      C.byref(ao), C.byref(self.opts.c()), _ptr(t),
+                                      C.byref(ao), C.byref(self.opts.c(self.n)), _ptr(t),
                                       _ptr(self.loss), _ptr(self.ws), self.nbytes, _stream()))
+        self.step_index += 1  # counted only once the library has taken the step
         return self.loss
 
     def _records(self):
         lib = L.load()
         mr = C.c_int32(0)
-        st = lib.tbr_tape_records(_ptr(self.ws), self.nbytes, C.byref(self.opts.c()), self.n,
+        st = lib.tbr_tape_records(_ptr(self.ws), self.nbytes, C.byref(self.opts.c(self.n)), self.n,
                                   C.byref(mr), _stream())
         return st, mr.value
 

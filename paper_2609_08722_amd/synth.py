@@ -105,6 +105,14 @@ def loop_theta(n: int, k: int, seed: int) -> np.ndarray:
     return np.concatenate([ta, td, tr, tc.reshape(-1), tp]).astype(np.float32)
 
 
+def coupling_coeffs(n: int, seed: int, amp: float = 0.15) -> np.ndarray:
+    """Per-stroke coefficients (c_1, c_2, c_3) of the calibrated coupling,
+    each U(-amp, amp): every profile stays above 1 - 3 amp (the fitted
+    coefficients of the paper are not available)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-amp, amp, size=(n, 3)).astype(np.float32)
+
+
 def make_program(n: int, k: int, seed: int, dist: StrokeDist = DIST_SMALL,
                  beta: float = 1.0, dtype=np.float32) -> dict:
     """Draw one program of ``n`` capsule strokes over a ``k``-colour palette."""

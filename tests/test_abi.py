@@ -42,7 +42,7 @@ def test_version(lib):
 
 def opts(**kw):
     base = dict(width=64, height=64, tau=1e-3, tau_min=0.7 / 64, tau_c=0.0, eps_floor=1e-3,
-                ckpt_interval=16, side_slots=4)
+                ckpt_interval=16, side_slots=4, transport=0, coupling=None)
     base.update(kw)
     return L.RenderOpts(*[base[f] for f, _ in L.RenderOpts._fields_])
 
@@ -170,3 +170,37 @@ def test_loop_step_checks_workspace_before_launching(lib):
     st = lib.tbr_fit_loop_step(10, 4, p, p, None, p, p, C.byref(w), C.byref(a), C.byref(opts()),
                                p, p, p, 64, None)
     assert st == L.TBR_E_INVALID and b"workspace" in lib.tbr_last_error()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_coupling_check_is_exact(lib, seed):
+    """tbr_coupling_check's minimum of g = 1 + sum_k c_k cos(4 pi k v)
+    against dense sampling of the definition; a profile that dips below 0
+    is rejected."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-0.6, 0.6, size=(200, 3)).astype(np.float32)
+    v = np.linspace(0.0, 0.25, 200001)
+    g = 1.0 + sum(c[:, k:k + 1].astype(np.float64) * np.cos(4 * np.pi * (k + 1) * v)[None]
+                  for k in range(3))
+    want = g.min()
+    got = C.c_float()
+    st = lib.tbr_coupling_check(c.ctypes.data_as(C.c_void_p), len(c), C.byref(got))
+    assert got.value == pytest.approx(want, abs=1e-6)
+    assert (st == L.TBR_OK) == (want > 0)
+    ok = c[g.min(1) > 0]
+    st = lib.tbr_coupling_check(ok.ctypes.data_as(C.c_void_p), len(ok), C.byref(got))
+    assert st == L.TBR_OK and got.value > 0
+
+
+def test_coupled_options_need_coefficients(lib):
+    o = opts(transport=L.TBR_TRANSPORT_COUPLED, coupling=None)
+    prog = L.Program(0, 1, None, None, None, None, None, None, C.c_void_p(16))
+    buf = C.create_string_buffer(1 << 16)
+    st = lib.tbr_render(C.byref(prog), C.byref(o), L.TBR_SOFT, None, None, None,
+                        C.cast(buf, C.c_void_p), 1 << 16, 0, None)
+    assert st == L.TBR_E_INVALID and b"coupling" in lib.tbr_last_error()
+    o = opts(transport=5)
+    st = lib.tbr_render(C.byref(prog), C.byref(o), L.TBR_SOFT, None, None, None,
+                        C.cast(buf, C.c_void_p), 1 << 16, 0, None)
+    assert st == L.TBR_E_INVALID and b"transport" in lib.tbr_last_error()
