@@ -19,7 +19,9 @@ from .binding import (  # noqa: F401
     map_jacobian,
     num_threads,
     phi,
+    phi_drops,
     psi,
+    psi_drops,
     render,
     backward,
     set_num_threads,

@@ -53,6 +53,8 @@ def _load():
         _lib.orc_phi.argtypes = [vp, i64, vp, vp, vp]
         _lib.orc_chart.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         _lib.orc_map_jacobian.argtypes = [i32, vp, dbl, i64, vp, vp, vp]
+        _lib.orc_psi_drops.argtypes = [vp, dbl, i64, vp, vp, vp]
+        _lib.orc_phi_drops.argtypes = [vp, i64, vp, vp]
         _lib.orc_render.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
         _lib.orc_render.restype = i32
         _lib.orc_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
@@ -123,15 +125,34 @@ def chart(stroke, pts, coupling=None, edge=False):
     return (sig, w, e) if edge else (sig, w)
 
 
+def psi_drops(stroke, pts, eps=1e-3):
+    """R_D's backward displacement of one stroke (16 drops) at points [n,2]."""
+    s = _stroke(stroke)
+    p = _f64(pts).reshape(-1, 2)
+    out = np.empty_like(p)
+    rec = np.empty(len(p), dtype=np.int32)
+    _load().orc_psi_drops(_ptr(s), float(eps), len(p), _ptr(p), _ptr(out), _ptr(rec))
+    return out, rec.astype(bool)
+
+
+def phi_drops(stroke, pts):
+    """R_D's forward displacement of one stroke at points [n,2]."""
+    s = _stroke(stroke)
+    p = _f64(pts).reshape(-1, 2)
+    out = np.empty_like(p)
+    _load().orc_phi_drops(_ptr(s), len(p), _ptr(p), _ptr(out))
+    return out
+
+
 def map_jacobian(which, stroke, pts, eps=1e-3, coupling=None):
-    """Exact Jacobian [n,2,7] of psi ('psi') or Phi ('phi') w.r.t.
-    (x, y, m_x, m_y, phi, L, r)."""
+    """Exact Jacobian [n,2,7] w.r.t. (x, y, m_x, m_y, phi, L, r) of psi
+    ('psi'), Phi ('phi') or R_D's displacements ('psi_drops', 'phi_drops')."""
     s = _stroke(stroke)
     p = _f64(pts).reshape(-1, 2)
     c = _coup(coupling)
     jac = np.empty((len(p), 2, 7))
-    _load().orc_map_jacobian(0 if which == "psi" else 1, _ptr(s), float(eps), len(p),
-                             _ptr(p), _ptr(jac), _ptr(c))
+    code = {"psi": 0, "phi": 1, "psi_drops": 2, "phi_drops": 3}[which]
+    _load().orc_map_jacobian(code, _ptr(s), float(eps), len(p), _ptr(p), _ptr(jac), _ptr(c))
     return jac
 
 
@@ -167,6 +188,8 @@ def _opts(width, height, tau, tau_min, tau_c, eps, transport, coup=None):
 
 def render(prog, width, height, *, tau=1e-3, tau_min=None, tau_c=0.0, eps=1e-3,
            transport=True, pixels=None, soft=True, hard=True, coupling=None):
+    # transport: True / 1 = the capsule renderer R_A, False / 0 = the
+    # inert-mark model R_U, 2 = R_D (sixteen drops per stroke)
     """Render a program (dict of arrays, see the synthetic generator) at pixel
     centres. Returns a dict with 'soft' [n,3], 'hard' [n,3], 'label', 'owner',
     'dmin', 'n_rec' (flat pixel order, or the order of ``pixels``).

@@ -19,6 +19,11 @@
 //     potential flow", Eq. coupling, Eq. profile): the area added along the
 //     leaf of centred fraction v is A_l(r) g(v), g(v) = 1 + sum_k c_k
 //     cos(4 pi k v), and the deposit is {u <= A_l(r) g(v)};
+//   * the two other renderers the paper scores with: the inert-mark model
+//     R_U (psi = id, Def. inert-mark) and R_D (Sec. "Transfer across
+//     transport constructions"): capsule coverage, but the displacement of
+//     stroke i is K = 16 drop maps (Lu 2012) of radius s, K pi s^2 = A_l(r),
+//     laid along the segment;
 //   * soft coverage: Sec. 5.1, Eq. (relax); alpha clamp 1 - 1e-7: Sec. 5.2;
 //   * colour model c = softmax(z / tau_c) P: Sec. 5.1;
 //   * gradient: plain reverse-mode chain rule over the state of Eq. (state),
@@ -260,6 +265,69 @@ void phi_map(const T& x, const T& y, const Stroke<T>& g, T& ox, T& oy) {
   reconstruct(c, g, sp, ox, oy);
 }
 
+// R_D's displacement. The drops sit at the centres of K equal pieces of the
+// segment and are laid in one sweep from its -e end to its +e end, so the
+// forward map inserts drop 0 first and the backward map undoes drop K-1
+// first. A drop of radius s at c moves a point at distance rho from c to
+// distance sqrt(rho^2 + s^2) on the same ray (forward) or back to
+// sqrt(rho^2 - s^2), floored at pi (rho^2 - s^2) >= (eps s)^2 (the capsule's
+// implemented floor, for the drop's own radius). Returns whether a floor
+// bound.
+const int kDropsK = 16;
+
+template <class T>
+void drop_centre(const Stroke<T>& g, int j, T& cx, T& cy, T& s2) {
+  T ell = val(g.L) < 0 ? -g.L : g.L;
+  double f = (j + 0.5) / kDropsK - 0.5;  // along e, in units of l
+  cx = g.mx + f * ell * m_cos(g.phi);
+  cy = g.my + f * ell * m_sin(g.phi);
+  s2 = steiner_area(ell, g.r) / (kDropsK * kPi);
+}
+
+template <class T>
+bool psi_drops(const T& x, const T& y, const Stroke<T>& g, double eps, T& ox, T& oy) {
+  T px = x, py = y;
+  bool rec = false;
+  for (int j = kDropsK - 1; j >= 0; --j) {
+    T cx, cy, s2;
+    drop_centre(g, j, cx, cy, s2);
+    T dx = px - cx, dy = py - cy;
+    T rho2 = dx * dx + dy * dy;
+    T C = kPi * (rho2 - s2);
+    T fl = eps * eps * s2 * kPi;  // (eps s)^2
+    if (val(C) < val(fl)) {
+      C = fl;
+      rec = true;
+    }
+    if (val(rho2) > 0) {
+      T k = m_sqrt(C / (kPi * rho2));
+      px = cx + dx * k;
+      py = cy + dy * k;
+    }
+  }
+  ox = px;
+  oy = py;
+  return rec;
+}
+
+template <class T>
+void phi_drops(const T& x, const T& y, const Stroke<T>& g, T& ox, T& oy) {
+  T px = x, py = y;
+  for (int j = 0; j < kDropsK; ++j) {
+    T cx, cy, s2;
+    drop_centre(g, j, cx, cy, s2);
+    T dx = px - cx, dy = py - cy;
+    T rho2 = dx * dx + dy * dy;
+    if (val(rho2) > 0) {
+      T k = m_sqrt((rho2 + s2) / rho2);
+      px = cx + dx * k;
+      py = cy + dy * k;
+    }
+  }
+  ox = px;
+  oy = py;
+}
+
 // Soft coverage, Eq. (relax), clamped at 1 - 1e-7: the signed distance from
 // the deposit's edge on the point's leaf (r, or the coupled leaf_edge) over
 // the width max(tau r, tau_min) of the stroke's half-width r.
@@ -291,7 +359,7 @@ struct Program {
 struct Opts {
   int32_t width, height;
   double tau, tau_min, tau_c, eps;
-  int32_t transport;       // 1 = displacing renderer R_A, 0 = inert-mark R_U
+  int32_t transport;       // 1 = capsule renderer R_A, 0 = inert-mark R_U, 2 = R_D (16 drops)
   const double* coupling;  // [N][3] c_1..c_3 per stroke (Eq. profile), or NULL: g = 1
 };
 
@@ -299,6 +367,18 @@ Stroke<double> stroke_at(const Program& p, const Opts& o, int i) {
   Stroke<double> g{p.cx[i], p.cy[i], p.angle[i], p.length[i], p.half_width[i]};
   g.coup = o.coupling ? o.coupling + 3 * size_t(i) : nullptr;
   return g;
+}
+
+// The displacement the renderer applies after stroke g (psi_i of Eq. chain):
+// the capsule map (or its calibrated coupling), the identity (R_U) or the
+// sixteen drops (R_D). Returns whether a floor bound.
+template <class T>
+bool transport_step(const Opts& o, const T& x, const T& y, const Stroke<T>& g, T& ox, T& oy) {
+  if (o.transport == 2) return psi_drops(x, y, g, o.eps, ox, oy);
+  if (o.transport == 1) return psi(x, y, g, o.eps, ox, oy);
+  ox = x;
+  oy = y;
+  return false;
 }
 
 int argmax_row(const double* z, int k) {
@@ -384,6 +464,22 @@ void orc_phi(const double* stroke, int64_t n, const double* pts, double* out,
   for (int64_t j = 0; j < n; ++j) phi_map(pts[2 * j], pts[2 * j + 1], g, out[2 * j], out[2 * j + 1]);
 }
 
+// R_D's backward / forward displacement of one stroke at a batch of points.
+void orc_psi_drops(const double* stroke, double eps, int64_t n, const double* pts, double* out,
+                   int32_t* rec) {
+  Stroke<double> g{stroke[0], stroke[1], stroke[2], stroke[3], stroke[4]};
+  for (int64_t j = 0; j < n; ++j) {
+    bool b = psi_drops(pts[2 * j], pts[2 * j + 1], g, eps, out[2 * j], out[2 * j + 1]);
+    if (rec) rec[j] = b ? 1 : 0;
+  }
+}
+
+void orc_phi_drops(const double* stroke, int64_t n, const double* pts, double* out) {
+  Stroke<double> g{stroke[0], stroke[1], stroke[2], stroke[3], stroke[4]};
+  for (int64_t j = 0; j < n; ++j)
+    phi_drops(pts[2 * j], pts[2 * j + 1], g, out[2 * j], out[2 * j + 1]);
+}
+
 // Distance to the segment, centred arclength fraction and the deposit's
 // edge on the point's leaf (diagnostics; edge may be NULL).
 void orc_chart(const double* stroke, int64_t n, const double* pts, double* sigma, double* w,
@@ -398,7 +494,8 @@ void orc_chart(const double* stroke, int64_t n, const double* pts, double* sigma
   }
 }
 
-// Exact Jacobians (dual numbers) of psi (which = 0) or Phi (which = 1):
+// Exact Jacobians (dual numbers) of psi (which = 0), Phi (1), or R_D's
+// backward (2) / forward (3) displacement:
 // jac[j] is 2 x 7, row-major, columns (x, y, m_x, m_y, phi, L, r).
 void orc_map_jacobian(int which, const double* stroke, double eps, int64_t n, const double* pts,
                       double* jac, const double* coup) {
@@ -421,8 +518,12 @@ void orc_map_jacobian(int which, const double* stroke, double eps, int64_t n, co
     Dual ox, oy;
     if (which == 0)
       psi(x, y, g, eps, ox, oy);
-    else
+    else if (which == 1)
       phi_map(x, y, g, ox, oy);
+    else if (which == 2)
+      psi_drops(x, y, g, eps, ox, oy);
+    else
+      phi_drops(x, y, g, ox, oy);
     for (int k = 0; k < ND; ++k) {
       jac[j * 14 + k] = ox.d[k];
       jac[j * 14 + 7 + k] = oy.d[k];
@@ -462,6 +563,7 @@ int orc_render(const orc_program* prog, const orc_opts* opts, int64_t n_pix, con
         double a = soft_alpha(sig, edge, g.r, o.tau, o.tau_min);
         for (int ch = 0; ch < 3; ++ch) C[ch] += T * a * col[size_t(i) * 3 + ch];
         T *= (1.0 - a);
+        if (o.transport == 2) rec = psi_drops(x, y, g, o.eps, ox, oy);
         nr += rec ? 1 : 0;
         if (o.transport) {
           x = ox;
@@ -484,12 +586,10 @@ int orc_render(const orc_program* prog, const orc_opts* opts, int64_t n_pix, con
           own = i;
           break;
         }
-        if (o.transport) {
-          double ox, oy;
-          psi(x, y, g, o.eps, ox, oy);
-          x = ox;
-          y = oy;
-        }
+        double ox, oy;
+        transport_step(o, x, y, g, ox, oy);
+        x = ox;
+        y = oy;
       }
       int lab = own >= 0 ? argmax_row(p.logits + size_t(own) * p.k, p.k) : 0;
       if (rgb_hard)
@@ -550,6 +650,7 @@ int orc_backward(const orc_program* prog, const orc_opts* opts, int64_t n_pix, c
           psi(x, y, g, o.eps, ox, oy, &sig, &edge);
           double a = soft_alpha(sig, edge, g.r, o.tau, o.tau_min);
           T *= (1.0 - a);
+          if (o.transport == 2) psi_drops(x, y, g, o.eps, ox, oy);
           if (o.transport) {
             x = ox;
             y = oy;
@@ -585,6 +686,7 @@ int orc_backward(const orc_program* prog, const orc_opts* opts, int64_t n_pix, c
           Dual ox, oy, sig, edge;
           psi(X, Y, g, o.eps, ox, oy, &sig, &edge);
           Dual a = soft_alpha(sig, edge, g.r, o.tau, o.tau_min);
+          if (o.transport == 2) psi_drops(X, Y, g, o.eps, ox, oy);
           if (!o.transport) {  // psi = id
             ox = X;
             oy = Y;
@@ -656,12 +758,10 @@ void orc_hard_points(const orc_program* prog, const orc_opts* opts, int64_t n, c
         own = i;
         break;
       }
-      if (o.transport) {
-        double ox, oy;
-        psi(x, y, g, o.eps, ox, oy);
-        x = ox;
-        y = oy;
-      }
+      double ox, oy;
+      transport_step(o, x, y, g, ox, oy);
+      x = ox;
+      y = oy;
     }
     owner[j] = own;
   }
