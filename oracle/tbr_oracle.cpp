@@ -294,7 +294,7 @@ bool psi_drops(const T& x, const T& y, const Stroke<T>& g, double eps, T& ox, T&
     T dx = px - cx, dy = py - cy;
     T rho2 = dx * dx + dy * dy;
     T C = kPi * (rho2 - s2);
-    T fl = eps * eps * s2 * kPi;  // (eps s)^2
+    T fl = eps * eps * s2;  // (eps s)^2, an area like C
     if (val(C) < val(fl)) {
       C = fl;
       rec = true;

@@ -49,6 +49,27 @@ def test_at_a_drop_sixteen_drops_are_one_drop(orc, r):
     assert np.max(np.abs(orc.phi_drops(g, p) - tb.drop_forward(g[:2], r, p))) <= 1e-13
 
 
+@pytest.mark.parametrize("eps", [1e-3, 1e-2])
+def test_floor_inside_a_drop(orc, eps):
+    """Inside the deposit each drop's map is floored like the capsule's
+    C >= (eps r)^2, for the drop's own radius s: pi (rho^2 - s^2) >=
+    (eps s)^2. At l = 0 the sixteen drops are concentric with s = r / 4, so
+    a point inside ends on the ray it started on, at pi rho'^2 = (eps s)^2."""
+    r = 0.03
+    g = stroke_for(0.0, r)
+    rng = np.random.default_rng(11)
+    ang = rng.random(500) * 2 * np.pi
+    rad = r * np.sqrt(rng.random(500)) * 0.9 + 1e-4
+    p = g[:2] + rad[:, None] * np.stack([np.cos(ang), np.sin(ang)], 1)
+    out, rec = orc.psi_drops(g, p, eps=eps)
+    assert rec.all()
+    s = r / 4
+    d = out - g[:2]
+    assert np.allclose(np.linalg.norm(d, axis=1), eps * s / math.sqrt(math.pi), rtol=1e-12)
+    assert np.allclose(np.arctan2(d[:, 1], d[:, 0]), np.arctan2(p[:, 1] - g[1], p[:, 0] - g[0]),
+                       atol=1e-12)
+
+
 @pytest.mark.parametrize("ell,r", SHAPES)
 def test_backward_inverts_the_textbook_sweep(orc, ell, r):
     """psi_D undoes the K textbook insertions laid from the -e end, and not
