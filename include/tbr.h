@@ -103,8 +103,23 @@ typedef struct tbr_program_grad {
  *     floor stays (eps r)^2. The coefficients are constants of the call:
  *     no gradient flows to them. g must be positive on every leaf (check a
  *     coefficient table with tbr_coupling_check); where it is not, the
- *     kernels take g = 0 and the result is meaningless. */
-enum { TBR_TRANSPORT_CAPSULE = 0, TBR_TRANSPORT_COUPLED = 1 };
+ *     kernels take g = 0 and the result is meaningless.
+ *   TBR_TRANSPORT_INERT: the inert-mark model R_U (Def. inert-mark): psi =
+ *     id, each stroke composited where it is drawn. Renders, adjoint and fit
+ *     steps; no side-table records are made.
+ *   TBR_TRANSPORT_DROPS16: the renderer R_D the paper scores with (Sec.
+ *     "Transfer across transport constructions"): capsule coverage, but the
+ *     displacement is K = 16 drop maps (Lu 2012) of radius s, K pi s^2 =
+ *     A_l(r), at the centres of 16 equal pieces of the segment, laid from its
+ *     -e end (e = (cos angle, sin angle)) and undone last to first, each
+ *     with the floor pi rho'^2 >= (eps s)^2. Soft and hard renders without a
+ *     tape only: a tape, the adjoint and the fit steps return TBR_E_INVALID. */
+enum {
+  TBR_TRANSPORT_CAPSULE = 0,
+  TBR_TRANSPORT_COUPLED = 1,
+  TBR_TRANSPORT_INERT = 2,
+  TBR_TRANSPORT_DROPS16 = 3
+};
 
 typedef struct tbr_render_opts {
   int32_t width, height;  /* 1 .. 16384 each */
@@ -114,7 +129,7 @@ typedef struct tbr_render_opts {
   float eps_floor;        /* floor constant eps of C >= (eps r)^2, > 0 (paper: 1e-3) */
   int32_t ckpt_interval;  /* position checkpoint interval k of the adjoint, >= 0 (0 = none) */
   int32_t side_slots;     /* per-pixel side-table capacity, >= 1 when a tape is written */
-  int32_t transport;      /* TBR_TRANSPORT_CAPSULE (0) or TBR_TRANSPORT_COUPLED */
+  int32_t transport;      /* a TBR_TRANSPORT_* value (0 = the capsule operator) */
   const float* coupling;  /* COUPLED: device [n_strokes * 3], (c_1, c_2, c_3) per stroke, read
                              by the call's stroke preparation; otherwise ignored (may be NULL) */
 } tbr_render_opts;

@@ -12,7 +12,7 @@ TBR_OK, TBR_PENDING = 0, 1
 TBR_E_INVALID, TBR_E_NOMEM, TBR_E_OVERFLOW, TBR_E_CAPACITY = -1, -2, -3, -4
 TBR_E_DEVICE, TBR_E_CANCELLED, TBR_E_NOTFOUND = -5, -6, -7
 TBR_HARD, TBR_SOFT = 1, 2
-TBR_TRANSPORT_CAPSULE, TBR_TRANSPORT_COUPLED = 0, 1
+TBR_TRANSPORT_CAPSULE, TBR_TRANSPORT_COUPLED, TBR_TRANSPORT_INERT, TBR_TRANSPORT_DROPS16 = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "TBR_OK", 1: "TBR_PENDING", -1: "TBR_E_INVALID", -2: "TBR_E_NOMEM",
                 -3: "TBR_E_OVERFLOW", -4: "TBR_E_CAPACITY", -5: "TBR_E_DEVICE",

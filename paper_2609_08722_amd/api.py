@@ -37,6 +37,9 @@ class Opts:
     # calibrated coupling (Eq. coupling, Eq. profile): a contiguous float32
     # CUDA tensor [N, 3] of (c_1, c_2, c_3) per stroke, or None (capsule map)
     coupling: "torch.Tensor | None" = None
+    # "inert" (R_U, psi = id) or "drops16" (R_D, renders only); None: the
+    # capsule map, or its coupling when coupling is given
+    transport: str | None = None
 
     def c(self, n_strokes: int | None = None) -> L.RenderOpts:
         """The C options; with n_strokes, also checks the coupling's size
@@ -47,11 +50,13 @@ class Opts:
             raise ValueError("coupling must be a contiguous float32 CUDA tensor [N, 3]")
         if cp is not None and n_strokes is not None and cp.numel() != 3 * n_strokes:
             raise ValueError(f"coupling has {cp.numel()} values, expected 3 x {n_strokes}")
+        if self.transport is not None and cp is not None:
+            raise ValueError("coupling applies to the capsule map only")
+        tr = {None: L.TBR_TRANSPORT_CAPSULE if cp is None else L.TBR_TRANSPORT_COUPLED,
+              "inert": L.TBR_TRANSPORT_INERT, "drops16": L.TBR_TRANSPORT_DROPS16}[self.transport]
         return L.RenderOpts(int(self.width), int(self.height), float(self.tau), float(tm),
                             float(self.tau_c), float(self.eps), int(self.ckpt),
-                            int(self.side_slots),
-                            L.TBR_TRANSPORT_CAPSULE if cp is None else L.TBR_TRANSPORT_COUPLED,
-                            None if cp is None else cp.data_ptr())
+                            int(self.side_slots), tr, None if cp is None else cp.data_ptr())
 
     @property
     def pixels(self) -> int:

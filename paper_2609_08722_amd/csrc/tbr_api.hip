@@ -165,9 +165,10 @@ tbr_status check_opts(const tbr_render_opts* o, bool soft, bool tape) {
   if (o->ckpt_interval < 0) return fail(TBR_E_INVALID, "ckpt_interval must be >= 0");
   if (tape && o->side_slots < 1) return fail(TBR_E_INVALID, "side_slots must be >= 1 with a tape");
   if (o->side_slots < 0) return fail(TBR_E_INVALID, "side_slots must be >= 0");
-  if (o->transport != TBR_TRANSPORT_CAPSULE && o->transport != TBR_TRANSPORT_COUPLED)
-    return fail(TBR_E_INVALID, "transport %d is not TBR_TRANSPORT_CAPSULE or _COUPLED",
-                o->transport);
+  if (o->transport < TBR_TRANSPORT_CAPSULE || o->transport > TBR_TRANSPORT_DROPS16)
+    return fail(TBR_E_INVALID, "transport %d is not a TBR_TRANSPORT_* value", o->transport);
+  if (tape && o->transport == TBR_TRANSPORT_DROPS16)
+    return fail(TBR_E_INVALID, "the 16-drop transport renders only: no tape, adjoint or fit");
   if (coupled(o) && !o->coupling)
     return fail(TBR_E_INVALID, "the coupled transport needs the coupling coefficients");
   return TBR_OK;
@@ -244,17 +245,18 @@ tbr_status launch_reduce(const tbr_program* p, const tbr_render_opts* o, const t
 
 // The fused fit kernel over the jobs' (job, tile) items; the cursor is
 // cleared by a fill kernel (no memset node if the caller captures a graph).
-tbr_status launch_fused(const FitJobsK& K, int* cursor, bool coup, hipStream_t st) {
+tbr_status launch_fused(const FitJobsK& K, int* cursor, int transport, hipStream_t st) {
   k_fill_i32<<<1, 64, 0, st>>>(cursor, 1, 0);
   tbr_status s = check_launch("fill");
   if (s) return s;
   {
     Timed tm("fit_fused", st);
     const int grid = std::min(K.n_items, 256 * 8);
-    if (coup)
-      k_fit_fused<true><<<grid, 256, 0, st>>>(K, cursor);
-    else
-      k_fit_fused<false><<<grid, 256, 0, st>>>(K, cursor);
+    switch (transport) {
+      case kCoupled: k_fit_fused<kCoupled><<<grid, 256, 0, st>>>(K, cursor); break;
+      case kInert: k_fit_fused<kInert><<<grid, 256, 0, st>>>(K, cursor); break;
+      default: k_fit_fused<kCapsule><<<grid, 256, 0, st>>>(K, cursor); break;
+    }
   }
   return check_launch("fit_fused");
 }
@@ -270,12 +272,20 @@ tbr_status launch_backward(const tbr_program* p, const tbr_render_opts* o, const
   dim3 grid(tiles_x(o), tiles_y(o));
   {
     Timed tm("replay", st);
-    if (coup)
-      k_replay<true><<<grid, 256, 0, st>>>(recs, coup, n, o->width, o->height, p->palette,
-                                           grad_rgb, t, partial);
-    else
-      k_replay<false><<<grid, 256, 0, st>>>(recs, nullptr, n, o->width, o->height, p->palette,
-                                            grad_rgb, t, partial);
+    const int W = o->width, H = o->height;
+    switch (o->transport) {
+      case kCoupled:
+        k_replay<kCoupled><<<grid, 256, 0, st>>>(recs, coup, n, W, H, p->palette, grad_rgb, t,
+                                                 partial);
+        break;
+      case kInert:
+        k_replay<kInert><<<grid, 256, 0, st>>>(recs, nullptr, n, W, H, p->palette, grad_rgb, t,
+                                               partial);
+        break;
+      default:
+        k_replay<kCapsule><<<grid, 256, 0, st>>>(recs, nullptr, n, W, H, p->palette, grad_rgb,
+                                                 t, partial);
+    }
   }
   tbr_status s = check_launch("replay");
   if (s) return s;
@@ -371,7 +381,7 @@ tbr_status fit_core(int32_t n_strokes, int32_t n_palette, float* params, float* 
   D.tiles_x = tiles_x(opts);
   D.item0 = 0;
   KJ.n_items = (int)n_tiles(opts);
-  if ((s = launch_fused(KJ, reinterpret_cast<int*>(ws + FL.cursor), coup != nullptr, st)))
+  if ((s = launch_fused(KJ, reinterpret_cast<int*>(ws + FL.cursor), opts->transport, st)))
     return s;
   k_loss_final<<<1, 256, 0, st>>>(lpart, (int)n_tiles(opts), 1.0f / (3.0f * (float)n_pixels(opts)),
                                   loss);
@@ -418,11 +428,23 @@ tbr_status tbr_render(const tbr_program* prog, const tbr_render_opts* opts, int3
     {
       Timed tm("trace_soft", st);
       const KSeed none{nullptr, nullptr, nullptr};
-      if (coup)
-        k_trace_soft<true><<<grid, 256, 0, st>>>(recs, coup, n, W, H, prog->palette, rgb, t, none);
-      else
-        k_trace_soft<false><<<grid, 256, 0, st>>>(recs, nullptr, n, W, H, prog->palette, rgb, t,
-                                                  none);
+      switch (opts->transport) {
+        case kCoupled:
+          k_trace_soft<kCoupled><<<grid, 256, 0, st>>>(recs, coup, n, W, H, prog->palette, rgb, t,
+                                                       none);
+          break;
+        case kInert:
+          k_trace_soft<kInert><<<grid, 256, 0, st>>>(recs, nullptr, n, W, H, prog->palette, rgb,
+                                                     t, none);
+          break;
+        case kDrops:
+          k_trace_soft<kDrops><<<grid, 256, 0, st>>>(recs, nullptr, n, W, H, prog->palette, rgb,
+                                                     t, none);
+          break;
+        default:
+          k_trace_soft<kCapsule><<<grid, 256, 0, st>>>(recs, nullptr, n, W, H, prog->palette,
+                                                       rgb, t, none);
+      }
     }
     if ((s = check_launch("trace_soft"))) return s;
   }
@@ -430,12 +452,23 @@ tbr_status tbr_render(const tbr_program* prog, const tbr_render_opts* opts, int3
     {
       Timed tm("trace_hard", st);
       float* hrgb = soft ? nullptr : rgb;
-      if (coup)
-        k_trace_hard<true><<<grid, 256, 0, st>>>(recs, coup, n, W, H, prog->palette, hrgb, label,
-                                                 owner);
-      else
-        k_trace_hard<false><<<grid, 256, 0, st>>>(recs, nullptr, n, W, H, prog->palette, hrgb,
-                                                  label, owner);
+      switch (opts->transport) {
+        case kCoupled:
+          k_trace_hard<kCoupled><<<grid, 256, 0, st>>>(recs, coup, n, W, H, prog->palette, hrgb,
+                                                       label, owner);
+          break;
+        case kInert:
+          k_trace_hard<kInert><<<grid, 256, 0, st>>>(recs, nullptr, n, W, H, prog->palette, hrgb,
+                                                     label, owner);
+          break;
+        case kDrops:
+          k_trace_hard<kDrops><<<grid, 256, 0, st>>>(recs, nullptr, n, W, H, prog->palette, hrgb,
+                                                     label, owner);
+          break;
+        default:
+          k_trace_hard<kCapsule><<<grid, 256, 0, st>>>(recs, nullptr, n, W, H, prog->palette,
+                                                       hrgb, label, owner);
+      }
     }
     if ((s = check_launch("trace_hard"))) return s;
   }
@@ -694,7 +727,7 @@ tbr_status tbr_fit_multi_step(const tbr_fit_job* jobs, int32_t n_jobs, void* wor
     items += (int)n_tiles(&J.opts);
   }
   K.n_items = items;
-  if ((s = launch_fused(K, reinterpret_cast<int*>(ws), coupled(&jobs[0].opts), st))) return s;
+  if ((s = launch_fused(K, reinterpret_cast<int*>(ws), jobs[0].opts.transport, st))) return s;
   for (int j = 0; j < n_jobs; ++j) {
     const tbr_fit_job& J = jobs[j];
     const FitLayout& FL = layouts[j];

@@ -289,6 +289,42 @@ __device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, boo
   return m;
 }
 
+// The displacement of the renderer R_D (Sec. "Transfer across transport
+// constructions"): K = 16 drop maps (Lu 2012) of radius s, K pi s^2 =
+// A_l(r), at the centres of K equal pieces of the segment, laid from its -e
+// end; the backward map undoes the last drop first. A drop at c takes the
+// point at distance rho from c to distance rho' = sqrt(rho^2 - s^2) on the
+// same ray, floored at pi (rho'^2) >= (eps s)^2. Each drop's map is
+// singular on its circle rho = s, and sixteen such circles lie around every
+// stroke, so the point's offset from each drop centre is formed in FP64 and
+// each drop's FP32 displacement (rho' / rho - 1) (p - c), written as
+// (rho'^2 - rho^2) / (rho^2 (1 + rho' / rho)) (p - c) without cancellation,
+// is added to the FP64 offset at once.
+constexpr int kNumDrops = 16;
+__device__ __forceinline__ void drops_backward(double& x, double& y, const StrokeRec& g) {
+  const float s2 = g.ar * (1.f / (kNumDrops * kPi));
+  // eps^2 = floor_c / r^2, so the floor on rho'^2 is floor_c s^2 / (pi r^2)
+  const float fl = g.r > 0.f ? g.floor_c * rcp(g.r * g.r) * (s2 * (1.f / kPi)) : 0.f;
+  const double ux = (double)(g.ell * g.ce), uy = (double)(g.ell * g.se);  // -e end to +e end
+  double ox = x - g.mx, oy = y - g.my;
+#pragma unroll
+  for (int j = kNumDrops - 1; j >= 0; --j) {
+    const double f = ((double)j + 0.5) * (1.0 / kNumDrops) - 0.5;
+    const float px = (float)fma(-f, ux, ox), py = (float)fma(-f, uy, oy);
+    const float rho2 = fmaf(px, px, py * py);
+    const float cq = rho2 - s2;
+    const bool floored = cq < fl;
+    const float num = floored ? fl - rho2 : -s2;  // rho'^2 - rho^2
+    const float inv = rho2 > 0.f ? rcp(rho2) : 0.f;
+    const float k = hw_sqrt((floored ? fl : cq) * inv);
+    const float sc = num * inv * rcp(1.f + k);
+    ox += (double)(px * sc);
+    oy += (double)(py * sc);
+  }
+  x = g.mx + ox;
+  y = g.my + oy;
+}
+
 // Apply a displacement (a, b) along (e, n), unfolded, to the FP64 state.
 __device__ __forceinline__ void step_by(double& x, double& y, float a, float b,
                                         const StrokeRec& g) {
@@ -364,6 +400,30 @@ struct VjpOut {
   float gx, gy;                          // lambda^x_i
   float gmx, gmy, gphi, gell, gr;        // stroke contributions
 };
+
+// The inert-mark model R_U (psi = id, Def. inert-mark): the point never
+// moves, so a stroke's step depends on its parameters only through the
+// coverage z = (r - sigma) / wd at the fixed point. Its contributions, given
+// mu = the adjoint of alpha (gx, gy are 0: the point's adjoint is not needed).
+__device__ __forceinline__ VjpOut vjp_cover_only(const Chart& c, const StrokeRec& g,
+                                                 const Cover& v, float mu) {
+  VjpOut o;
+  const float zb = v.clamped ? 0.f : mu * v.alpha * v.q;
+  const float zw = zb * g.inv_wd;
+  o.gr = zw * fmaf(-v.z, g.dwd_dr, 1.f);
+  // sigma = sqrt(H^2 + E^2), E = S - l/2 on the caps (sin th = 0 on the flank)
+  const float hb = -zw * c.cs, eb = -zw * c.sn;
+  const float ssb = c.sgs * eb, shb = c.sgh * hb;
+  const float gx = fmaf(ssb, g.ce, -(shb * g.se));
+  const float gy = fmaf(ssb, g.se, shb * g.ce);
+  o.gx = 0.f;
+  o.gy = 0.f;
+  o.gmx = -gx;
+  o.gmy = -gy;
+  o.gphi = fmaf(ssb, c.h, -(shb * c.s));
+  o.gell = -0.5f * eb;
+  return o;
+}
 
 // kCover = false drops the coverage terms (a far stroke, alpha = 0 to FP32).
 // kCoupled: the leaf's area G = A_l(r) g(w) and edge rl depend on w, l and r

@@ -161,7 +161,7 @@ struct SoftOut {
   int nrec;          // records pushed (floor bound)
 };
 
-template <bool kTape, bool kC = false>
+template <bool kTape, int kT = kCapsule>
 __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs,
                                               const float4* __restrict__ coup, int n,
                                               const PixelId& id, int width, int height,
@@ -190,7 +190,7 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
       next_ck -= k;
     }
     Chart c = chart(x, y, g);
-    const Leaf lf = leaf_at<kC>(c, g, coup, i);
+    const Leaf lf = leaf_at<kT == kCoupled>(c, g, coup, i);
     // Coverage and compositing, unless the stroke is far from every pixel
     // of the wave: then alpha < 7e-13, 1 - alpha rounds to 1 and T and C
     // are unchanged to FP32 rounding. Lanes past a ragged canvas edge trace
@@ -206,17 +206,21 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
       tm *= v.q;
       renorm(tm, te);
     }
-    // backward map with the implemented floor; record where it binds
-    Move mv = displace(c, g, true, lf);
-    if (mv.floored) {
-      if (write_tape && nrec < tape.side_slots) {
-        size_t o = (size_t)nrec * P + id.p;
-        tape.side_idx[o] = i;
-        tape.side_xy[o] = make_double2(x, y);
+    if constexpr (kT == kDrops) {
+      drops_backward(x, y, g);  // R_D: rendered only, no tape
+    } else if constexpr (kT != kInert) {
+      // backward map with the implemented floor; record where it binds
+      Move mv = displace(c, g, true, lf);
+      if (mv.floored) {
+        if (write_tape && nrec < tape.side_slots) {
+          size_t o = (size_t)nrec * P + id.p;
+          tape.side_idx[o] = i;
+          tape.side_xy[o] = make_double2(x, y);
+        }
+        ++nrec;
       }
-      ++nrec;
+      advance(x, y, c, mv, g);
     }
-    advance(x, y, c, mv, g);
   }
   float t = trans_value(tm, te);
   SoftOut o;
@@ -234,7 +238,7 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
 
 // Hard trace of one pixel per lane: first footprint hit going N -> 1; lanes
 // retire on a hit and the wave leaves the stroke loop once all have retired.
-template <bool kC = false>
+template <int kT = kCapsule>
 __device__ __forceinline__ void hard_pixel(const StrokeRec* __restrict__ recs,
                                            const float4* __restrict__ coup, int n,
                                            const PixelId& id, int width, int height, int& own,
@@ -249,19 +253,21 @@ __device__ __forceinline__ void hard_pixel(const StrokeRec* __restrict__ recs,
     const StrokeRec g = load_rec(recs, i);
     if (!done) {
       Chart c = chart(x, y, g);
-      const Leaf lf = leaf_at<kC>(c, g, coup, i);
+      const Leaf lf = leaf_at<kT == kCoupled>(c, g, coup, i);
       if (c.sig <= lf.r) {  // closed footprint
         done = true;
         own = i;
         lab = g.label;
-      } else {
+      } else if constexpr (kT == kDrops) {
+        drops_backward(x, y, g);
+      } else if constexpr (kT != kInert) {
         advance(x, y, c, displace(c, g, true, lf), g);
       }
     }
   }
 }
 
-template <bool kC>
+template <int kT>
 __global__ void __launch_bounds__(256)
     k_trace_soft(const StrokeRec* __restrict__ recs, const float4* __restrict__ coup, int n,
                  int width, int height, const float* __restrict__ palette, float* __restrict__ rgb,
@@ -269,8 +275,8 @@ __global__ void __launch_bounds__(256)
   PixelId id = pixel_of_tile(blockIdx.x, blockIdx.y, width, height);
   const int P = width * height;
   SoftOut o = tape.ckpt_xy
-                  ? soft_pixel<true, kC>(recs, coup, n, id, width, height, palette, tape)
-                  : soft_pixel<false, kC>(recs, coup, n, id, width, height, palette, tape);
+                  ? soft_pixel<true, kT>(recs, coup, n, id, width, height, palette, tape)
+                  : soft_pixel<false, kT>(recs, coup, n, id, width, height, palette, tape);
   if (id.active && rgb) {
     rgb[3 * (size_t)id.p + 0] = o.cr;
     rgb[3 * (size_t)id.p + 1] = o.cg;
@@ -307,7 +313,7 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-template <bool kC>
+template <int kT>
 __global__ void __launch_bounds__(256)
     k_trace_hard(const StrokeRec* __restrict__ recs, const float4* __restrict__ coup, int n,
                  int width, int height, const float* __restrict__ palette,
@@ -315,7 +321,7 @@ __global__ void __launch_bounds__(256)
                  int32_t* __restrict__ owner) {
   PixelId id = pixel_of_tile(blockIdx.x, blockIdx.y, width, height);
   int own, lab;
-  hard_pixel<kC>(recs, coup, n, id, width, height, own, lab);
+  hard_pixel<kT>(recs, coup, n, id, width, height, own, lab);
   if (id.active) {
     if (owner) owner[id.p] = own;
     if (label) label[id.p] = lab;
@@ -465,7 +471,7 @@ using ReduceLds = float[2][16][kChunk + 1][8];
 // The replay of one 16x16 tile by the whole block (all 256 threads must
 // call it). lcr, lcg, lcb: this lane's dL/dR; prow: the tile's partial row
 // [n + 1][8] (row n = background colour gradient).
-template <bool kC = false>
+template <int kT = kCapsule>
 __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
                                             const float4* __restrict__ coup, int n,
                                             const PixelId& id, int width, int height,
@@ -514,6 +520,55 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
 
   // checkpointed states x_k, x_2k, ... (< x_n); x_{i+1} is the input of stroke i
   int next_ck = (k > 0 && k < n) ? k - 1 : 0x7fffffff;
+  if constexpr (kT == kInert) {
+    // R_U: the point stays where it is; only T is regenerated (Eq. rT),
+    // reset at the checkpoints, and each stroke's coverage differentiated.
+    for (int c0 = 0; c0 < n; c0 += kChunk) {
+      const int buf = (c0 / kChunk) & 1;
+      const int cn = min(kChunk, n - c0);
+      for (int j = 0; j < cn; ++j) {
+        const int i = c0 + j;
+        const StrokeRec g = load_rec(recs, i);
+        const bool ck = i == next_ck;
+        if (ck) next_ck = next_ck + k + 1 < n ? next_ck + k : 0x7fffffff;
+        Chart ca = chart(x, y, g);
+        float tot = 0.f;
+        if (ck && id.active) {
+          const float2 ckt = tape.ckpt_t[(size_t)((i + 1) / k) * P + id.p];
+          tm = ckt.x;
+          te = (int)ckt.y;
+        }
+        if (!wave_all((g.r - ca.sig) * g.inv_wd < kFarZ)) {
+          Cover cv = cover(ca.sig, g, g.r);
+          if (!ck) {
+            tm *= cv.inv_q;
+            renorm(tm, te);
+          }
+          float t = trans_value(tm, te);
+          float lc = fmaf(lcr, g.cr, fmaf(lcg, g.cg, lcb * g.cb));
+          float mu = t * (lc - lt);
+          float ta = t * cv.alpha;
+          lt = fmaf(cv.q, lt, cv.alpha * lc);
+          VjpOut vo = vjp_cover_only(ca, g, cv, mu);
+          float v[8] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
+          tot = row_sums8(v, lane);
+        }
+        if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
+      }
+      __syncthreads();
+      {
+        const int j = threadIdx.x >> 3, vv = threadIdx.x & 7;
+        if (j < cn) {
+          float s = 0.f;
+#pragma unroll
+          for (int q = 0; q < 16; ++q) s += lds[buf][q][j][vv];
+          prow[(size_t)(c0 + j) * 8 + vv] = s;
+        }
+      }
+    }
+    return;
+  }
+  constexpr bool kC = kT == kCoupled;
   for (int c0 = 0; c0 < n; c0 += kChunk) {
     const int buf = (c0 / kChunk) & 1;
     const int cn = min(kChunk, n - c0);
@@ -685,7 +740,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
 }
 
 
-template <bool kC>
+template <int kT>
 __global__ void __launch_bounds__(256)
     k_replay(const StrokeRec* __restrict__ recs, const float4* __restrict__ coup, int n,
              int width, int height, const float* __restrict__ palette,
@@ -699,7 +754,7 @@ __global__ void __launch_bounds__(256)
     lcg = grad_rgb[3 * (size_t)id.p + 1];
     lcb = grad_rgb[3 * (size_t)id.p + 2];
   }
-  replay_tile<kC>(recs, coup, n, id, width, height, palette, lcr, lcg, lcb, tape,
+  replay_tile<kT>(recs, coup, n, id, width, height, palette, lcr, lcg, lcb, tape,
                   partial + (size_t)tile * (n + 1) * 8, lds);
 }
 
@@ -714,7 +769,7 @@ __global__ void __launch_bounds__(256)
 // The forward and the replay share one register allocation here; asking for
 // 5 waves per SIMD (96 VGPRs, instead of 111 at 4 waves) spills only values
 // that live across a tile or a 16-stroke chunk, never inside a stroke loop.
-template <bool kC>
+template <int kT>
 __global__ void __launch_bounds__(256, 5) k_fit_fused(FitJobsK jobs, int* __restrict__ cursor) {
   __shared__ ReduceLds lds;
   __shared__ float red[256];
@@ -731,7 +786,7 @@ __global__ void __launch_bounds__(256, 5) k_fit_fused(FitJobsK jobs, int* __rest
     const int tile = it - J.item0;
     PixelId id = pixel_of_tile(tile % J.tiles_x, tile / J.tiles_x, J.width, J.height);
     const int P = J.width * J.height;
-    SoftOut o = soft_pixel<true, kC>(J.recs, J.coup, J.n, id, J.width, J.height, J.palette,
+    SoftOut o = soft_pixel<true, kT>(J.recs, J.coup, J.n, id, J.width, J.height, J.palette,
                                      J.tape);
     float lcr = 0.f, lcg = 0.f, lcb = 0.f, sq = 0.f;
     if (id.active) {
@@ -754,7 +809,7 @@ __global__ void __launch_bounds__(256, 5) k_fit_fused(FitJobsK jobs, int* __rest
       __syncthreads();
     }
     if (threadIdx.x == 0) J.loss_part[tile] = red[0];
-    replay_tile<kC>(J.recs, J.coup, J.n, id, J.width, J.height, J.palette, lcr, lcg, lcb,
+    replay_tile<kT>(J.recs, J.coup, J.n, id, J.width, J.height, J.palette, lcr, lcg, lcb,
                     J.tape, J.partial + (size_t)tile * (J.n + 1) * 8, lds);
   }
 }
@@ -1041,17 +1096,24 @@ __global__ void __launch_bounds__(256)
 }  // namespace tbr
 
 namespace tbr {
-// Both variants of the per-pixel kernels: the uniform insertion and the
-// calibrated coupling.
-#define TBR_INSTANTIATE(C)                                                                      \
-  template __global__ void k_trace_soft<C>(const StrokeRec*, const float4*, int, int, int,      \
+// The per-pixel kernels for each transport: the capsule map, its calibrated
+// coupling, the inert-mark model and (rendering only) the sixteen drops.
+#define TBR_INSTANTIATE_RENDER(T)                                                               \
+  template __global__ void k_trace_soft<T>(const StrokeRec*, const float4*, int, int, int,      \
                                            const float*, float*, KTape, KSeed);                 \
-  template __global__ void k_trace_hard<C>(const StrokeRec*, const float4*, int, int, int,      \
-                                           const float*, float*, int32_t*, int32_t*);           \
-  template __global__ void k_replay<C>(const StrokeRec*, const float4*, int, int, int,          \
+  template __global__ void k_trace_hard<T>(const StrokeRec*, const float4*, int, int, int,      \
+                                           const float*, float*, int32_t*, int32_t*);
+#define TBR_INSTANTIATE_ADJOINT(T)                                                              \
+  template __global__ void k_replay<T>(const StrokeRec*, const float4*, int, int, int,          \
                                        const float*, const float*, KTape, float*);              \
-  template __global__ void k_fit_fused<C>(FitJobsK, int*);
-TBR_INSTANTIATE(false)
-TBR_INSTANTIATE(true)
-#undef TBR_INSTANTIATE
+  template __global__ void k_fit_fused<T>(FitJobsK, int*);
+TBR_INSTANTIATE_RENDER(kCapsule)
+TBR_INSTANTIATE_RENDER(kCoupled)
+TBR_INSTANTIATE_RENDER(kInert)
+TBR_INSTANTIATE_RENDER(kDrops)
+TBR_INSTANTIATE_ADJOINT(kCapsule)
+TBR_INSTANTIATE_ADJOINT(kCoupled)
+TBR_INSTANTIATE_ADJOINT(kInert)
+#undef TBR_INSTANTIATE_RENDER
+#undef TBR_INSTANTIATE_ADJOINT
 }  // namespace tbr

@@ -98,15 +98,20 @@ __global__ void k_window_map(const float* th, float* nat, int n, int kpal, KWind
 __global__ void k_reg_loss(const float* nat, int n, KWindow w, float* loss);
 __global__ void k_window_adam(float* th, const float* g_nat, float* m, float* v, int n, int kpal,
                               KWindow w, KAdam a, const int32_t* records, int capacity);
-// kC: calibrated coupling (coup = per-stroke profile cubics), else uniform.
-template <bool kC>
+// Transport variants of the per-pixel kernels (the values of
+// tbr_render_opts.transport): the capsule map, its calibrated coupling (coup
+// = per-stroke profile cubics), the inert-mark model (no displacement), and
+// the sixteen drops of R_D (soft and hard renders only).
+constexpr int kCapsule = 0, kCoupled = 1, kInert = 2, kDrops = 3;
+
+template <int kT>
 __global__ void k_trace_soft(const StrokeRec* recs, const float4* coup, int n, int width,
                              int height, const float* palette, float* rgb, KTape tape, KSeed seed);
-template <bool kC>
+template <int kT>
 __global__ void k_trace_hard(const StrokeRec* recs, const float4* coup, int n, int width,
                              int height, const float* palette, float* rgb, int32_t* label,
                              int32_t* owner);
-template <bool kC>
+template <int kT>
 __global__ void k_replay(const StrokeRec* recs, const float4* coup, int n, int width, int height,
                          const float* palette, const float* grad_rgb, KTape tape, float* partial);
 __global__ void k_sum_tiles(const float* partial, int rows8, int n_tiles, int tiles_per_group,
@@ -118,7 +123,7 @@ __global__ void k_palette_grad(const float* pal_terms, int n, int kpal, const fl
 __global__ void k_loss_final(const float* part, int n_part, float inv_count, float* loss);
 __global__ void k_adam(float* prm, const float* grd, float* m, float* v, int n, int kpal, KAdam a,
                        const int32_t* records, int capacity);
-template <bool kC>
+template <int kT>
 __global__ void k_fit_fused(FitJobsK jobs, int* cursor);
 __global__ void k_serve(const ServeDesc* descs, const uint2* items, int n_items, int* cursor);
 __global__ void k_serve_prep(const ServePrep* preps, int n_req);

@@ -1,0 +1,131 @@
+"""GPU parity of the two other renderers the paper scores with, against the
+FP64 oracle: the inert-mark model R_U (psi = id; forward, adjoint and fit
+step) and R_D (sixteen drop maps per stroke; soft and hard renders)."""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import group_errors, hard_parity, log, require_gpu
+from paper_2609_08722_amd import _lib as L
+from paper_2609_08722_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+GROUPS = ("cx", "cy", "angle", "length", "half_width", "logits", "palette")
+ORC_T = {"inert": 0, "drops16": 2}
+
+
+def forward_check(orc, prog, W, H, transport, name, tau=1e-3, tau_c=0.0, soft_tol=1e-4):
+    require_gpu()
+    dp = api.to_device(prog)
+    o = api.Opts(W, H, tau=tau, tau_c=tau_c, transport=transport)
+    soft = api.render(dp, o, "soft")["rgb"].cpu().numpy().reshape(-1, 3)
+    hard = api.render(dp, o, "hard")
+    ref = orc.render(prog, W, H, tau=tau, tau_min=0.7 / W, tau_c=tau_c,
+                     transport=ORC_T[transport])
+    err = np.abs(soft - ref["soft"])
+    exempt, bad = hard_parity(hard["owner"].cpu().numpy(), hard["label"].cpu().numpy(), ref)
+    log(f"[{transport} {name}] {W}x{H} N={len(prog['cx'])}: soft max err {err.max():.3e} "
+        f"(p99.9 {np.quantile(err, 0.999):.3e}, {int((err.max(1) > 1e-5).sum())} pixels "
+        f"> 1e-5); hard exempt {exempt}, mismatches {bad}")
+    assert err.max() <= soft_tol
+    assert bad == 0
+    return hard
+
+
+@pytest.mark.parametrize("transport", ["inert", "drops16"])
+def test_forward_64x64(orc, transport):
+    forward_check(orc, synth.make_program(50, 8, 1), 64, 64, transport, "seed1")
+
+
+@pytest.mark.parametrize("transport", ["inert", "drops16"])
+def test_forward_ragged_relative_width(orc, transport):
+    forward_check(orc, synth.make_program(80, 8, 8, beta=2.0), 70, 45, transport, "ragged",
+                  tau=0.35, tau_c=1.0)
+
+
+@pytest.mark.parametrize("transport", ["inert", "drops16"])
+def test_forward_256_n500(orc, transport):
+    w = synth.WORKLOADS["adj256x256_n500"]
+    prog = synth.workload_program(w)
+    hard = forward_check(orc, prog, 256, 256, transport, w.name, tau_c=w.tau_c)
+    cap = api.render(api.to_device(prog), api.Opts(256, 256), "hard")
+    assert (cap["owner"] != hard["owner"]).float().mean().item() > 0.01
+
+
+def test_drops16_renders_only():
+    require_gpu()
+    dp = api.to_device(synth.make_program(20, 4, 2))
+    o = api.Opts(32, 32, tau_c=1.0, transport="drops16")
+    with pytest.raises(L.TbrError):
+        api.render(dp, o, "soft", tape=True)
+    tgt = torch.zeros(32, 32, 3, device="cuda")
+    with pytest.raises(L.TbrError):
+        api.FitState(dp, o).step(tgt)
+
+
+def gpu_grads(prog, W, H, seed_rgb, tau_c=1.0, ckpt=256):
+    dp = api.to_device(prog)
+    o = api.Opts(W, H, tau_c=tau_c, ckpt=ckpt, side_slots=4, transport="inert")
+    out = api.render(dp, o, "soft", tape=True)
+    assert out["tape"].max_records == 0
+    g = api.render_backward(dp, out["tape"], torch.from_numpy(seed_rgb.astype(np.float32)).cuda())
+    return {k: v.cpu().numpy() for k, v in g.items()}
+
+
+def orc_grads(orc, prog, W, H, seed_rgb, tau_c=1.0):
+    r = orc.backward(prog, W, H, seed_rgb, tau=1e-3, tau_min=0.7 / W, tau_c=tau_c,
+                     transport=False)
+    out = {f: r["geom"][q] for q, f in enumerate(GROUPS[:5])}
+    out["logits"], out["palette"] = r["logits"], r["palette"]
+    return out
+
+
+def compare(g, r, name):
+    for f in GROUPS:
+        rel, cos = group_errors(g[f], r[f])
+        log(f"[inert {name}] {f:10s} rel {rel:.2e} cos {cos:.9f}")
+        assert rel <= 1e-3, f
+
+
+@pytest.mark.parametrize("ckpt", [8, 256])
+def test_inert_adjoint_small(orc, ckpt):
+    require_gpu()
+    W, H = 48, 40
+    prog = synth.make_program(40, 6, 11, beta=2.0)
+    seed = np.random.default_rng(3).normal(size=(W * H, 3)) * 1e-3
+    compare(gpu_grads(prog, W, H, seed, ckpt=ckpt), orc_grads(orc, prog, W, H, seed),
+            f"small k={ckpt}")
+
+
+def test_inert_adjoint_256_n500(orc):
+    require_gpu()
+    w = synth.WORKLOADS["adj256x256_n500"]
+    prog = synth.workload_program(w)
+    tp = synth.make_program(w.n_strokes, w.n_palette, w.target_seed, w.dist, w.beta)
+    target = orc.render(tp, w.width, w.height, soft=False)["hard"]
+    R = orc.render(prog, w.width, w.height, tau=1e-3, tau_min=0.7 / w.width, tau_c=w.tau_c,
+                   hard=False, transport=False)["soft"]
+    seed = 2.0 * (R - target) / R.size
+    compare(gpu_grads(prog, w.width, w.height, seed, tau_c=w.tau_c, ckpt=w.ckpt),
+            orc_grads(orc, prog, w.width, w.height, seed, tau_c=w.tau_c), w.name)
+
+
+def test_inert_fit_step_equals_decomposed_path():
+    require_gpu()
+    W, H = 64, 48
+    prog = api.to_device(synth.make_program(60, 6, 31, beta=2.0))
+    target = api.render(api.to_device(synth.make_program(60, 6, 32)), api.Opts(W, H),
+                        "hard")["rgb"]
+    o = api.Opts(W, H, tau_c=1.0, ckpt=16, side_slots=4, transport="inert")
+    out = api.render(prog, o, "soft", tape=True)
+    sc = torch.tensor(2.0 / (3.0 * W * H), dtype=torch.float32, device="cuda")
+    g = api.render_backward(prog, out["tape"], (out["rgb"] - target) * sc)
+    fit = api.FitState(prog, o, api.Adam(lr_centre=0, lr_angle=0, lr_length=0, lr_width=0,
+                                         lr_logits=0, lr_palette=0))
+    loss = fit.step(target)
+    mse = torch.mean((out["rgb"].double() - target.double()) ** 2).item()
+    assert abs(loss.item() - mse) <= 1e-6 * mse
+    got = api.unpack(fit.grads, fit.n, fit.k)
+    for f in api.FIELDS:
+        assert torch.equal(got[f].reshape(-1), g[f].reshape(-1)), f
