@@ -14,6 +14,7 @@ Parity status: every function here is pinned by the CPU tests under
 from .binding import (  # noqa: F401
     build,
     chart,
+    compensate,
     hard_points,
     lib_path,
     map_jacobian,

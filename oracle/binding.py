@@ -54,6 +54,7 @@ def _load():
         _lib.orc_chart.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         _lib.orc_map_jacobian.argtypes = [i32, vp, dbl, i64, vp, vp, vp]
         _lib.orc_psi_drops.argtypes = [vp, dbl, i64, vp, vp, vp]
+        _lib.orc_compensate.argtypes = [vp, dbl, i32, i32, vp, vp, vp, vp, vp]
         _lib.orc_phi_drops.argtypes = [vp, i64, vp, vp]
         _lib.orc_render.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
         _lib.orc_render.restype = i32
@@ -248,3 +249,18 @@ def hard_points(prog, pts, *, eps=1e-3, transport=True, coupling=None):
     own = np.empty(len(p), dtype=np.int32)
     _load().orc_hard_points(C.byref(pr.s), C.byref(o), len(p), _ptr(p), _ptr(own))
     return own
+
+
+def compensate(prog, *, eps=1e-3, endpoint=False, skip=False):
+    """Closed-form compensation of an inert-mark program: returns the
+    compensated program (dict) and the blocked-step count of each stroke."""
+    pr = _Prog(prog)
+    n = pr.n
+    out = {k: np.empty(n) for k in ("cx", "cy", "angle", "length")}
+    blocked = np.empty(n, dtype=np.int32)
+    _load().orc_compensate(C.byref(pr.s), float(eps), int(bool(endpoint)), int(bool(skip)),
+                           _ptr(out["cx"]), _ptr(out["cy"]), _ptr(out["angle"]),
+                           _ptr(out["length"]), _ptr(blocked))
+    res = {k: _f64(prog[k]).copy() for k in ("half_width", "logits", "palette")}
+    res.update(out)
+    return res, blocked

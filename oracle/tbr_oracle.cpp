@@ -24,6 +24,10 @@
 //     transport constructions"): capsule coverage, but the displacement of
 //     stroke i is K = 16 drop maps (Lu 2012) of radius s, K pi s^2 = A_l(r),
 //     laid along the segment;
+//   * the closed-form compensation baseline (Sec. "Closed-form compensation
+//     baseline", Table compensation, Lemma obstruction): each stroke of an
+//     inert-mark program is moved to the pre-image of its anchor (or of
+//     both segment ends) under every later, already compensated stroke;
 //   * soft coverage: Sec. 5.1, Eq. (relax); alpha clamp 1 - 1e-7: Sec. 5.2;
 //   * colour model c = softmax(z / tau_c) P: Sec. 5.1;
 //   * gradient: plain reverse-mode chain rule over the state of Eq. (state),
@@ -764,6 +768,58 @@ void orc_hard_points(const orc_program* prog, const orc_opts* opts, int64_t n, c
       y = oy;
     }
     owner[j] = own;
+  }
+}
+
+// Closed-form compensation of an inert-mark program (Sec. "Closed-form
+// compensation baseline"), written as its definition: for i = N-1 .. 0,
+// stroke i's anchor a_i = m_i - (L_i / 2) e_i (endpoint = 1: also its end
+// m_i + (L_i / 2) e_i) is pre-imaged through the later strokes j = N-1 down
+// to i+1, in their compensated geometry, by the backward maps psi_j with the
+// floor (eps r_j)^2. A step is blocked when the point lies in K_j (sigma' <=
+// r_j): no pre-image exists there (Lemma obstruction); it is then clamped by
+// the extended psi_j, or left out (skip = 1). The anchor variant keeps the
+// offset L e; the endpoint variant takes the segment between the two
+// pre-images (its angle is kept if they coincide). Radii, logits and palette
+// are unchanged. Outputs [N]: cx, cy, angle, length of the compensated
+// program, and the number of blocked steps of each stroke.
+void orc_compensate(const orc_program* prog, double eps, int32_t endpoint, int32_t skip,
+                    double* cx, double* cy, double* angle, double* length, int32_t* blocked) {
+  Program p = to_prog(prog);
+  const int N = p.n;
+  for (int i = N - 1; i >= 0; --i) {
+    const double ce = std::cos(p.angle[i]), se = std::sin(p.angle[i]), L = p.length[i];
+    double pts[2][2] = {{p.cx[i] - 0.5 * L * ce, p.cy[i] - 0.5 * L * se},
+                        {p.cx[i] + 0.5 * L * ce, p.cy[i] + 0.5 * L * se}};
+    const int npts = endpoint ? 2 : 1;
+    int nb = 0;
+    for (int j = N - 1; j > i; --j) {
+      Stroke<double> g{cx[j], cy[j], angle[j], length[j], p.half_width[j]};
+      for (int q = 0; q < npts; ++q) {
+        Chart<double> c = chart(pts[q][0], pts[q][1], g);
+        const bool inside = c.sigma <= g.r;
+        nb += inside ? 1 : 0;
+        if (inside && skip) continue;
+        double ox, oy;
+        psi(pts[q][0], pts[q][1], g, eps, ox, oy);
+        pts[q][0] = ox;
+        pts[q][1] = oy;
+      }
+    }
+    blocked[i] = nb;
+    if (endpoint) {
+      const double dx = pts[1][0] - pts[0][0], dy = pts[1][1] - pts[0][1];
+      const double len = std::sqrt(dx * dx + dy * dy);
+      cx[i] = 0.5 * (pts[0][0] + pts[1][0]);
+      cy[i] = 0.5 * (pts[0][1] + pts[1][1]);
+      angle[i] = len > 0 ? std::atan2(dy, dx) : p.angle[i];
+      length[i] = len;
+    } else {
+      cx[i] = pts[0][0] + 0.5 * L * ce;
+      cy[i] = pts[0][1] + 0.5 * L * se;
+      angle[i] = p.angle[i];
+      length[i] = L;
+    }
   }
 }
 
