@@ -43,7 +43,7 @@ FLOPS_REPLAY = 291   # replay step: chart, Phi displacement, advance, VJP, wave 
 # HBM bytes per k_fit_fused launch at the bench workload, from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
 # in the same runs; valid only for the kernel sources it was measured on.
-TRAFFIC = {"sha": "b1ca4cde4e99bea8", "bytes": 361.9e6 + 588.0e6}
+TRAFFIC = {"sha": "9c1ffadbc2b35662", "bytes": 359.8e6 + 588.3e6}
 
 
 def kernel_sha():
@@ -162,6 +162,39 @@ def api_forms(w, prog, opts, target, iters=20, warm=5):
         t = np.array([a.elapsed_time(b) for a, b in ev])
         out[name] = {"median_ms": float(np.median(t)), "min_ms": float(t.min()),
                      "pixel_strokes_per_s": P * N / (np.median(t) * 1e-3)}
+    return out
+
+
+def compensation_benchmark(w, prog, reps=5):
+    """The closed-form compensation pass over the 2000-stroke program (as an
+    inert-mark program): 1,999,000 anchor / 3,998,000 endpoint point maps in
+    N sequential steps of one workgroup, GPU time per pass, with the FP64
+    oracle's single-threaded pass beside it."""
+    import torch
+    import oracle
+    from paper_2609_08722_amd import api
+    dp = api.to_device(prog)
+    stream = torch.cuda.current_stream()
+    n = w.n_strokes
+    out = {"strokes": n}
+    for endpoint in (False, True):
+        name = "endpoint" if endpoint else "anchor"
+        api.compensate(dp, endpoint=endpoint)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(reps):
+            _, blocked = api.compensate(dp, endpoint=endpoint)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        maps = n * (n - 1) // 2 * (2 if endpoint else 1)
+        t0 = time.perf_counter()
+        oracle.compensate(prog, endpoint=endpoint)
+        cpu_s = time.perf_counter() - t0
+        out[name] = {"ms": ms, "point_maps": maps, "point_maps_per_s": maps / (ms * 1e-3),
+                     "blocked_strokes": int((blocked > 0).sum().item()),
+                     "oracle_1_thread_s": cpu_s}
     return out
 
 
@@ -338,6 +371,8 @@ def main():
                     help="skip the 8-job batched fit comparison")
     ap.add_argument("--no-fit-loop", action="store_true",
                     help="skip the 240-step fitting loop")
+    ap.add_argument("--no-compensation", action="store_true",
+                    help="skip the closed-form compensation pass")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="length of the Poisson serving replay (0 = skip)")
     ap.add_argument("--serve-warmup", type=float, default=1.0,
@@ -545,6 +580,9 @@ def main():
     if not args.no_batched_fit:
         out["batched_fit"] = batched_fit_benchmark()
         log(f"[bench] batched fit: {out['batched_fit']}")
+    if not args.no_compensation:
+        out["compensation"] = compensation_benchmark(w, prog)
+        log(f"[bench] compensation: {out['compensation']}")
     if not args.no_fit_loop:
         out["fit_loop"] = fit_loop_benchmark()
         log(f"[bench] fit loop: {out['fit_loop']}")

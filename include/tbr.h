@@ -134,6 +134,34 @@ typedef struct tbr_render_opts {
                              by the call's stroke preparation; otherwise ignored (may be NULL) */
 } tbr_render_opts;
 
+/* ---------------------------------------------------------------------------
+ * Closed-form compensation baseline (Sec. "Closed-form compensation
+ * baseline", Table compensation, Lemma obstruction): an inert-mark program
+ * is turned into one whose strokes, drawn under the capsule transport, land
+ * where the inert program drew them. From the last stroke to the first, the
+ * anchor a_i = m_i - (L_i / 2) e_i of stroke i (endpoint != 0: also its end
+ * m_i + (L_i / 2) e_i) is pre-imaged through the backward maps of all later
+ * strokes in their compensated geometry: N(N-1)/2 point maps (twice that for
+ * the endpoint variant). The anchor variant keeps the offset L_i e_i; the
+ * endpoint variant takes the segment between the two pre-images (angle kept
+ * when they coincide). A step whose point lies in a later footprint (sigma'
+ * <= r_j) is blocked: no pre-image exists; it is clamped by the extended map
+ * with the floor (eps_floor r_j)^2, or left out (skip_blocked != 0).
+ * ------------------------------------------------------------------------- */
+
+/* Device workspace bytes of tbr_compensate (the pending points, FP64). */
+size_t tbr_compensate_workspace_bytes(int32_t n_strokes, int32_t endpoint);
+
+/* inert: the program (device). Outputs, device [n_strokes], written: the
+ * compensated cx, cy, angle, length (half-widths, logits and palette are
+ * unchanged) and the number of blocked steps of each stroke. eps_floor > 0.
+ * One workgroup runs the N sequential steps on the stream. TBR_E_INVALID for
+ * NULL outputs (allowed when n_strokes is 0), a bad program or a short
+ * workspace. */
+tbr_status tbr_compensate(const tbr_program* inert, float eps_floor, int32_t endpoint,
+                          int32_t skip_blocked, float* cx, float* cy, float* angle, float* length,
+                          int32_t* blocked, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Exact positivity check of the coupled profiles (Sec. 4: g is a cubic in
  * cos 4 pi v on [-1, 1], so its minimum is at an end or at a root of its
  * derivative). coupling: HOST [n_strokes * 3]. Writes the smallest value of

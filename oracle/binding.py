@@ -54,7 +54,8 @@ def _load():
         _lib.orc_chart.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         _lib.orc_map_jacobian.argtypes = [i32, vp, dbl, i64, vp, vp, vp]
         _lib.orc_psi_drops.argtypes = [vp, dbl, i64, vp, vp, vp]
-        _lib.orc_compensate.argtypes = [vp, dbl, i32, i32, vp, vp, vp, vp, vp]
+        _lib.orc_compensate.argtypes = [vp, dbl, i32, i32, vp, vp, vp, vp, vp, vp, vp,
+                                        vp, vp, vp, vp, vp]
         _lib.orc_phi_drops.argtypes = [vp, i64, vp, vp]
         _lib.orc_render.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
         _lib.orc_render.restype = i32
@@ -251,16 +252,31 @@ def hard_points(prog, pts, *, eps=1e-3, transport=True, coupling=None):
     return own
 
 
-def compensate(prog, *, eps=1e-3, endpoint=False, skip=False):
+def compensate(prog, *, eps=1e-3, endpoint=False, skip=False, with_dmin=False, later=None,
+               with_amp=False):
     """Closed-form compensation of an inert-mark program: returns the
-    compensated program (dict) and the blocked-step count of each stroke."""
+    compensated program (dict) and the blocked-step count of each stroke.
+    with_dmin: also each stroke's closest approach |sigma' - r_j| to a later
+    footprint's edge and smallest sigma' at a blocked step. later: a dict of
+    cx, cy, angle, length [N] to pre-image through instead (each stroke is
+    then the compensation step alone, given that later geometry). with_amp:
+    also each stroke's largest error growth from any step to its chain's end
+    (Frobenius norm of the Jacobian product)."""
     pr = _Prog(prog)
     n = pr.n
     out = {k: np.empty(n) for k in ("cx", "cy", "angle", "length")}
     blocked = np.empty(n, dtype=np.int32)
+    dmin = np.empty(n)
+    smin = np.empty(n)
+    lat = None if later is None else {k: _f64(later[k]).reshape(n) for k in
+                                      ("cx", "cy", "angle", "length")}
+    lp = [None] * 4 if lat is None else [_ptr(lat[k]) for k in ("cx", "cy", "angle", "length")]
+    amp = np.empty(n) if with_amp else None
     _load().orc_compensate(C.byref(pr.s), float(eps), int(bool(endpoint)), int(bool(skip)),
                            _ptr(out["cx"]), _ptr(out["cy"]), _ptr(out["angle"]),
-                           _ptr(out["length"]), _ptr(blocked))
+                           _ptr(out["length"]), _ptr(blocked), _ptr(dmin), _ptr(smin), *lp,
+                           _ptr(amp))
     res = {k: _f64(prog[k]).copy() for k in ("half_width", "logits", "palette")}
     res.update(out)
-    return res, blocked
+    extra = ((dmin, smin) if with_dmin else ()) + ((amp,) if with_amp else ())
+    return (res, blocked) + extra

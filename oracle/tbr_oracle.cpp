@@ -782,24 +782,51 @@ void orc_hard_points(const orc_program* prog, const orc_opts* opts, int64_t n, c
 // offset L e; the endpoint variant takes the segment between the two
 // pre-images (its angle is kept if they coincide). Radii, logits and palette
 // are unchanged. Outputs [N]: cx, cy, angle, length of the compensated
-// program, and the number of blocked steps of each stroke.
+// program, the number of blocked steps of each stroke, and (may be NULL)
+// dmin, the smallest |sigma' - r_j| its points met on the way, and smin, the
+// smallest sigma' at a blocked step (a point on a later segment has no
+// defined side or, at a drop, direction: its clamp is ill-conditioned).
+// later (may be NULL): pre-image through these later strokes (cx, cy, angle,
+// length [N]) instead of the ones this call compensates -- each stroke is
+// then the compensation step alone, given the later geometry. amp (may be
+// NULL): the largest Frobenius norm, over the steps of a stroke's chains, of
+// the Jacobian from that step's point to the chain's end (dual numbers): how
+// much an error made at any step can grow by the end.
 void orc_compensate(const orc_program* prog, double eps, int32_t endpoint, int32_t skip,
-                    double* cx, double* cy, double* angle, double* length, int32_t* blocked) {
+                    double* cx, double* cy, double* angle, double* length, int32_t* blocked,
+                    double* dmin, double* smin, const double* later_cx, const double* later_cy,
+                    const double* later_angle, const double* later_length, double* amp) {
   Program p = to_prog(prog);
   const int N = p.n;
+  const bool given = later_cx && later_cy && later_angle && later_length;
   for (int i = N - 1; i >= 0; --i) {
     const double ce = std::cos(p.angle[i]), se = std::sin(p.angle[i]), L = p.length[i];
     double pts[2][2] = {{p.cx[i] - 0.5 * L * ce, p.cy[i] - 0.5 * L * se},
                         {p.cx[i] + 0.5 * L * ce, p.cy[i] + 0.5 * L * se}};
     const int npts = endpoint ? 2 : 1;
     int nb = 0;
+    double dm = INFINITY, sm = INFINITY;
+    std::vector<double> jac[2];  // per point: the steps' 2x2 Jacobians, row-major
     for (int j = N - 1; j > i; --j) {
-      Stroke<double> g{cx[j], cy[j], angle[j], length[j], p.half_width[j]};
+      Stroke<double> g = given ? Stroke<double>{later_cx[j], later_cy[j], later_angle[j],
+                                                later_length[j], p.half_width[j]}
+                               : Stroke<double>{cx[j], cy[j], angle[j], length[j], p.half_width[j]};
       for (int q = 0; q < npts; ++q) {
         Chart<double> c = chart(pts[q][0], pts[q][1], g);
+        dm = std::min(dm, std::fabs(c.sigma - g.r));
         const bool inside = c.sigma <= g.r;
+        if (inside) sm = std::min(sm, c.sigma);
         nb += inside ? 1 : 0;
         if (inside && skip) continue;
+        if (amp) {
+          Dual X(pts[q][0]), Y(pts[q][1]);
+          X.d[0] = 1;
+          Y.d[1] = 1;
+          Stroke<Dual> gd{Dual(g.mx), Dual(g.my), Dual(g.phi), Dual(g.L), Dual(g.r)};
+          Dual OX, OY;
+          psi(X, Y, gd, eps, OX, OY);
+          jac[q].insert(jac[q].end(), {OX.d[0], OX.d[1], OY.d[0], OY.d[1]});
+        }
         double ox, oy;
         psi(pts[q][0], pts[q][1], g, eps, ox, oy);
         pts[q][0] = ox;
@@ -807,6 +834,22 @@ void orc_compensate(const orc_program* prog, double eps, int32_t endpoint, int32
       }
     }
     blocked[i] = nb;
+    if (dmin) dmin[i] = dm;
+    if (smin) smin[i] = sm;
+    if (amp) {
+      double a = 1.0;
+      for (int q = 0; q < npts; ++q) {
+        double S[4] = {1, 0, 0, 1};  // product of the Jacobians from a step to the end
+        for (size_t t = jac[q].size(); t >= 4; t -= 4) {
+          const double* J = &jac[q][t - 4];
+          const double P[4] = {S[0] * J[0] + S[1] * J[2], S[0] * J[1] + S[1] * J[3],
+                               S[2] * J[0] + S[3] * J[2], S[2] * J[1] + S[3] * J[3]};
+          std::copy(P, P + 4, S);
+          a = std::max(a, std::sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2] + S[3] * S[3]));
+        }
+      }
+      amp[i] = a;
+    }
     if (endpoint) {
       const double dx = pts[1][0] - pts[0][0], dy = pts[1][1] - pts[0][1];
       const double len = std::sqrt(dx * dx + dy * dy);

@@ -107,6 +107,8 @@ SIGNATURES = {
     "tbr_fit_multi_step": (_i32, [_vp, _i32, _vp, _sz, _vp]),
     "tbr_fit_multi_records": (_i32, [_vp, _i32, _vp, _sz, _vp, _vp]),
     "tbr_coupling_check": (_i32, [_vp, _i32, _vp]),
+    "tbr_compensate_workspace_bytes": (_sz, [_i32, _i32]),
+    "tbr_compensate": (_i32, [_vp, C.c_float, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "tbr_window_map": (_i32, [_i32, _i32, _vp, _vp, _vp, _vp]),
     "tbr_fit_loop_step": (_i32, [_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                  _vp, _sz, _vp]),

@@ -177,6 +177,25 @@ def render_backward(prog: dict, tape: Tape, grad_rgb: torch.Tensor) -> dict:
     return grads
 
 
+def compensate(prog: dict, endpoint: bool = False, skip_blocked: bool = False,
+               eps: float = 1e-3):
+    """Closed-form compensation of an inert-mark program (tbr_compensate):
+    returns the compensated program and each stroke's blocked-step count."""
+    lib = L.load()
+    cp = c_program(prog)
+    n = cp.n_strokes
+    dev = prog["cx"].device
+    out = {f: prog[f].clone() for f in FIELDS}
+    blocked = torch.zeros(n, dtype=torch.int32, device=dev)
+    nbytes = lib.tbr_compensate_workspace_bytes(n, int(endpoint))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    L.check(lib.tbr_compensate(C.byref(cp), float(eps), int(endpoint), int(skip_blocked),
+                               _ptr(out["cx"]), _ptr(out["cy"]), _ptr(out["angle"]),
+                               _ptr(out["length"]), _ptr(blocked), _ptr(ws), nbytes, _stream()))
+    return out, blocked
+
+
+
 class TBRRender(torch.autograd.Function):
     """rgb = R(program) (soft render) with the replay adjoint as backward."""
 

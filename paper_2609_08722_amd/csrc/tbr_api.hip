@@ -595,6 +595,35 @@ tbr_status tbr_fit_loop_step(int32_t n_strokes, int32_t n_palette, float* theta,
   return check_launch("window_adam");
 }
 
+size_t tbr_compensate_workspace_bytes(int32_t n_strokes, int32_t endpoint) {
+  if (n_strokes < 0) return 0;
+  return align_up((size_t)(n_strokes > 0 ? n_strokes : 1) * (endpoint ? 2 : 1) * sizeof(double2));
+}
+
+tbr_status tbr_compensate(const tbr_program* inert, float eps_floor, int32_t endpoint,
+                          int32_t skip_blocked, float* cx, float* cy, float* angle, float* length,
+                          int32_t* blocked, void* workspace, size_t workspace_bytes, void* stream) {
+  tbr_status s;
+  if ((s = check_prog(inert))) return s;
+  if (!(eps_floor > 0.f) || !std::isfinite(eps_floor))
+    return fail(TBR_E_INVALID, "eps_floor must be > 0");
+  if (inert->n_strokes == 0) return TBR_OK;  // nothing to write (outputs may be NULL)
+  if (!cx || !cy || !angle || !length || !blocked || !workspace)
+    return fail(TBR_E_INVALID, "null argument");
+  const size_t need = tbr_compensate_workspace_bytes(inert->n_strokes, endpoint);
+  if (workspace_bytes < need)
+    return fail(TBR_E_INVALID, "workspace %zu bytes < required %zu", workspace_bytes, need);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  {
+    Timed tm("compensate", st);
+    k_compensate<<<1, kCompThreadsK, 0, st>>>(kprog(inert), eps_floor, endpoint ? 1 : 0,
+                                               skip_blocked ? 1 : 0,
+                                               static_cast<double2*>(workspace), cx, cy, angle,
+                                               length, blocked);
+  }
+  return check_launch("compensate");
+}
+
 tbr_status tbr_coupling_check(const float* coupling, int32_t n_strokes, float* min_g) {
   if (!coupling || n_strokes < 0) return fail(TBR_E_INVALID, "null argument");
   // g in W = cos(4 pi v) is the cubic a0 + a1 W + a2 W^2 + a3 W^3 on [-1, 1]:

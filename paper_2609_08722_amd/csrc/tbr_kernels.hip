@@ -1096,6 +1096,102 @@ __global__ void __launch_bounds__(256)
 }  // namespace tbr
 
 namespace tbr {
+
+// ---------------------------------------------------------------------------
+// Closed-form compensation of an inert-mark program (Sec. "Closed-form
+// compensation baseline"). Stroke i's anchor (and, for the endpoint variant,
+// its end) must be pre-imaged through every later stroke in that stroke's
+// compensated geometry, so the strokes are finished one at a time, last
+// first. The N(N-1)/2 point maps are reordered into N sequential steps:
+// before step k the pending points of strokes 0..k have been pre-imaged
+// through strokes N-1..k+1, so stroke k's are final; step k builds stroke
+// k's compensated record and then pushes the points of strokes 0..k-1
+// through its backward map, all in parallel. One workgroup runs the steps,
+// so a step's barrier is a workgroup barrier. A step inside a later
+// footprint (sigma' <= r) is blocked (Lemma obstruction): the extended map
+// clamps it with the floor (eps r)^2, or it is skipped.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kCompThreadsK)
+    k_compensate(KProgram p, float eps, int endpoint, int skip, double2* __restrict__ pts,
+                 float* __restrict__ ocx, float* __restrict__ ocy, float* __restrict__ oangle,
+                 float* __restrict__ olength, int32_t* __restrict__ blocked) {
+  __shared__ StrokeRec rec;
+  const int N = p.n, np = endpoint ? 2 : 1;
+  for (int i = threadIdx.x; i < N; i += kCompThreadsK) {
+    const float c = cosf(p.angle[i]), sn = sinf(p.angle[i]), hl = 0.5f * p.length[i];
+    pts[np * i] = make_double2((double)p.cx[i] - (double)(hl * c), (double)p.cy[i] - (double)(hl * sn));
+    if (endpoint)
+      pts[2 * i + 1] = make_double2((double)p.cx[i] + (double)(hl * c), (double)p.cy[i] + (double)(hl * sn));
+    blocked[i] = 0;
+  }
+  __syncthreads();
+  for (int k = N - 1; k >= 0; --k) {
+    if (threadIdx.x == 0) {
+      // stroke k is final: its compensated geometry and its backward map
+      const double2 a = pts[np * k];
+      float ce = cosf(p.angle[k]), se = sinf(p.angle[k]), ang = p.angle[k], len = p.length[k];
+      double mx, my;
+      if (endpoint) {
+        const double2 b = pts[2 * k + 1];
+        const double dx = b.x - a.x, dy = b.y - a.y;
+        const double d = sqrt(dx * dx + dy * dy);
+        mx = 0.5 * (a.x + b.x);
+        my = 0.5 * (a.y + b.y);
+        len = (float)d;
+        if (d > 0.0) {
+          ce = (float)(dx / d);
+          se = (float)(dy / d);
+          ang = (float)atan2(dy, dx);
+        }
+      } else {
+        mx = a.x + (double)(0.5f * len * ce);
+        my = a.y + (double)(0.5f * len * se);
+      }
+      ocx[k] = (float)mx;
+      ocy[k] = (float)my;
+      oangle[k] = ang;
+      olength[k] = len;
+      StrokeRec g{};
+      const float ell = fabsf(len), r = p.half_width[k];
+      g.mx = mx;
+      g.my = my;
+      g.ce = ce;
+      g.se = se;
+      g.ell = ell;
+      g.hl = 0.5f * ell;
+      g.two_ell = ell + ell;
+      g.r = r;
+      g.ar = r * fmaf(kPi, r, ell + ell);
+      g.per_r = fmaf(kTwoPi, r, ell + ell);
+      g.floor_c = (eps * r) * (eps * r);
+      rec = g;
+    }
+    __syncthreads();
+    if (k > 0) {
+      const StrokeRec g = rec;
+      const Leaf lf = uniform_leaf(g);
+      for (int i = threadIdx.x; i < k; i += kCompThreadsK) {
+        int nb = 0;
+        for (int q = 0; q < np; ++q) {
+          double2 v = pts[np * i + q];
+          const Chart c = chart(v.x, v.y, g);
+          const bool inside = c.sig <= g.r;
+          nb += inside ? 1 : 0;
+          if (!(inside && skip)) {
+            advance(v.x, v.y, c, displace(c, g, true, lf), g);
+            pts[np * i + q] = v;
+          }
+        }
+        if (nb) blocked[i] += nb;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace tbr
+
+namespace tbr {
 // The per-pixel kernels for each transport: the capsule map, its calibrated
 // coupling, the inert-mark model and (rendering only) the sixteen drops.
 #define TBR_INSTANTIATE_RENDER(T)                                                               \

@@ -128,5 +128,9 @@ __global__ void k_fit_fused(FitJobsK jobs, int* cursor);
 __global__ void k_serve(const ServeDesc* descs, const uint2* items, int n_items, int* cursor);
 __global__ void k_serve_prep(const ServePrep* preps, int n_req);
 __global__ void k_fill_i32(int32_t* p, int n, int v);
+constexpr int kCompThreadsK = 1024;  // the compensation's one workgroup
+__global__ void k_compensate(KProgram p, float eps, int endpoint, int skip, double2* pts,
+                             float* ocx, float* ocy, float* oangle, float* olength,
+                             int32_t* blocked);
 
 }  // namespace tbr

@@ -214,3 +214,19 @@ def test_drops_transport_has_no_tape(lib):
     st = lib.tbr_render(C.byref(prog), C.byref(o), L.TBR_SOFT, None, None, None,
                         C.cast(buf, C.c_void_p), 1 << 20, 1, None)
     assert st == L.TBR_E_INVALID and b"16-drop" in lib.tbr_last_error()
+
+
+def test_compensate_validation(lib):
+    """Host-side checks of tbr_compensate (nothing is launched)."""
+    buf = C.create_string_buffer(64)
+    p = C.cast(buf, C.c_void_p)
+    empty = L.Program(0, 1, None, None, None, None, None, None, C.c_void_p(16))
+    assert lib.tbr_compensate(C.byref(empty), 1e-3, 1, 0, None, None, None, None, None, None, 0,
+                              None) == L.TBR_OK
+    prog = L.Program(10, 2, p, p, p, p, p, p, p)
+    assert lib.tbr_compensate(C.byref(prog), 0.0, 0, 0, p, p, p, p, p, p, 1 << 20,
+                              None) == L.TBR_E_INVALID
+    assert lib.tbr_compensate(C.byref(prog), 1e-3, 1, 0, p, p, p, p, p, p, 64,
+                              None) == L.TBR_E_INVALID
+    assert b"workspace" in lib.tbr_last_error()
+    assert lib.tbr_compensate_workspace_bytes(10, 1) >= 10 * 2 * 16

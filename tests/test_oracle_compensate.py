@@ -111,3 +111,16 @@ def test_endpoint_variant_moves_both_ends(orc):
     a_end = np.array([ends(end, i)[0] for i in range(len(prog["cx"]))])
     assert np.mean(np.abs(end["length"] - prog["length"]) > 1e-9) > 0.2
     assert np.any(np.abs(a_anc - a_end).max(1) > 1e-9)  # later geometry differs
+
+
+@pytest.mark.parametrize("endpoint", [False, True])
+def test_stepwise_mode_reproduces_the_pass(orc, endpoint):
+    """Pre-imaging each stroke through given later geometry, when that
+    geometry is the pass's own result, is the pass itself."""
+    prog = inert_program()
+    out, blocked, dmin, smin = orc.compensate(prog, endpoint=endpoint, with_dmin=True)
+    again, b2, d2, s2 = orc.compensate(prog, endpoint=endpoint, with_dmin=True, later=out)
+    for f in ("cx", "cy", "angle", "length"):
+        assert np.array_equal(again[f], out[f])
+    assert np.array_equal(blocked, b2) and np.array_equal(dmin, d2) and np.array_equal(smin, s2)
+    assert np.all(np.isinf(smin[blocked == 0])) and np.all(smin[blocked > 0] <= out["half_width"].max())
