@@ -107,6 +107,21 @@ def _check_prog(prog: dict):
     return n, k
 
 
+def validate_program(prog: dict) -> None:
+    """Value checks the library leaves to its caller (it does not read
+    device arrays on the host): every array finite, half-widths > 0,
+    palette in [0, 1]. Synchronises; raises ValueError."""
+    _check_prog(prog)
+    for f in FIELDS:
+        if prog[f].numel() and not bool(torch.isfinite(prog[f]).all()):
+            raise ValueError(f"{f} holds a NaN or an infinity")
+    if prog["half_width"].numel() and float(prog["half_width"].min()) <= 0.0:
+        raise ValueError("half_width must be > 0")
+    pal = prog["palette"]
+    if float(pal.min()) < 0.0 or float(pal.max()) > 1.0:
+        raise ValueError("palette values must lie in [0, 1]")
+
+
 def c_program(prog: dict) -> L.Program:
     n, k = _check_prog(prog)
     return L.Program(n, k, *[_ptr(prog[f]) for f in FIELDS])
@@ -259,6 +274,7 @@ class FitState:
     def __init__(self, prog: dict, opts: Opts, adam: Adam | None = None):
         prog = to_device(prog) if not isinstance(prog["cx"], torch.Tensor) or not prog["cx"].is_cuda else prog
         self.n, self.k = _check_prog(prog)
+        validate_program(prog)
         self.opts = opts
         self.adam = adam or Adam()
         self.params = pack(prog)
@@ -406,6 +422,7 @@ class Server:
             k = np.asarray(prog["palette"]).reshape(-1, 3).shape[0]
             cp = L.Program(n, k, *([None] * 7))
         else:
+            validate_program(prog)
             cp = c_program(prog)
         pid = C.c_uint64()
         L.check(lib.tbr_serve_register_program(self.h, C.byref(cp), C.byref(pid)))

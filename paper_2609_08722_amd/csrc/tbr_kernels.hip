@@ -1104,18 +1104,68 @@ namespace tbr {
 // compensated geometry, so the strokes are finished one at a time, last
 // first. The N(N-1)/2 point maps are reordered into N sequential steps:
 // before step k the pending points of strokes 0..k have been pre-imaged
-// through strokes N-1..k+1, so stroke k's are final; step k builds stroke
-// k's compensated record and then pushes the points of strokes 0..k-1
-// through its backward map, all in parallel. One workgroup runs the steps,
-// so a step's barrier is a workgroup barrier. A step inside a later
-// footprint (sigma' <= r) is blocked (Lemma obstruction): the extended map
-// clamps it with the floor (eps r)^2, or it is skipped.
+// through strokes N-1..k+1, so stroke k's are final; step k pushes the
+// points of strokes 0..k-1 through stroke k's backward map, all in
+// parallel, and the thread that finishes stroke k-1's points builds its
+// compensated record for the next step (two LDS slots, alternating). One
+// workgroup runs the steps, so a step's barrier is a workgroup barrier. A
+// step inside a later footprint (sigma' <= r) is blocked (Lemma
+// obstruction): the extended map clamps it with the floor (eps r)^2, or it
+// is skipped.
 // ---------------------------------------------------------------------------
+
+// Compensated geometry and backward-map record of stroke k from its final
+// points (anchor, and end for the endpoint variant); writes the outputs.
+__device__ __forceinline__ void comp_record(const KProgram& p, float eps, int endpoint, int k,
+                                            const double2* __restrict__ pts, float* ocx,
+                                            float* ocy, float* oangle, float* olength,
+                                            StrokeRec& out) {
+  const int np = endpoint ? 2 : 1;
+  const double2 a = pts[np * k];
+  float ang = p.angle[k], len = p.length[k];
+  float ce = cosf(ang), se = sinf(ang);
+  double mx, my;
+  if (endpoint) {
+    const double2 b = pts[2 * k + 1];
+    const float dx = (float)(b.x - a.x), dy = (float)(b.y - a.y);
+    const float d = sqrtf(fmaf(dx, dx, dy * dy));
+    mx = 0.5 * (a.x + b.x);
+    my = 0.5 * (a.y + b.y);
+    len = d;
+    if (d > 0.f) {
+      ce = dx / d;
+      se = dy / d;
+      ang = atan2f(dy, dx);
+    }
+  } else {
+    mx = a.x + (double)(0.5f * len * ce);
+    my = a.y + (double)(0.5f * len * se);
+  }
+  ocx[k] = (float)mx;
+  ocy[k] = (float)my;
+  oangle[k] = ang;
+  olength[k] = len;
+  StrokeRec g{};
+  const float ell = fabsf(len), r = p.half_width[k];
+  g.mx = mx;
+  g.my = my;
+  g.ce = ce;
+  g.se = se;
+  g.ell = ell;
+  g.hl = 0.5f * ell;
+  g.two_ell = ell + ell;
+  g.r = r;
+  g.ar = r * fmaf(kPi, r, ell + ell);
+  g.per_r = fmaf(kTwoPi, r, ell + ell);
+  g.floor_c = (eps * r) * (eps * r);
+  out = g;
+}
+
 __global__ void __launch_bounds__(kCompThreadsK)
     k_compensate(KProgram p, float eps, int endpoint, int skip, double2* __restrict__ pts,
                  float* __restrict__ ocx, float* __restrict__ ocy, float* __restrict__ oangle,
                  float* __restrict__ olength, int32_t* __restrict__ blocked) {
-  __shared__ StrokeRec rec;
+  __shared__ StrokeRec rec[2];
   const int N = p.n, np = endpoint ? 2 : 1;
   for (int i = threadIdx.x; i < N; i += kCompThreadsK) {
     const float c = cosf(p.angle[i]), sn = sinf(p.angle[i]), hl = 0.5f * p.length[i];
@@ -1124,66 +1174,28 @@ __global__ void __launch_bounds__(kCompThreadsK)
       pts[2 * i + 1] = make_double2((double)p.cx[i] + (double)(hl * c), (double)p.cy[i] + (double)(hl * sn));
     blocked[i] = 0;
   }
+  // the last stroke has no later stroke: its points are final as drawn
+  if ((int)threadIdx.x == (N - 1) % kCompThreadsK)
+    comp_record(p, eps, endpoint, N - 1, pts, ocx, ocy, oangle, olength, rec[(N - 1) & 1]);
   __syncthreads();
-  for (int k = N - 1; k >= 0; --k) {
-    if (threadIdx.x == 0) {
-      // stroke k is final: its compensated geometry and its backward map
-      const double2 a = pts[np * k];
-      float ce = cosf(p.angle[k]), se = sinf(p.angle[k]), ang = p.angle[k], len = p.length[k];
-      double mx, my;
-      if (endpoint) {
-        const double2 b = pts[2 * k + 1];
-        const double dx = b.x - a.x, dy = b.y - a.y;
-        const double d = sqrt(dx * dx + dy * dy);
-        mx = 0.5 * (a.x + b.x);
-        my = 0.5 * (a.y + b.y);
-        len = (float)d;
-        if (d > 0.0) {
-          ce = (float)(dx / d);
-          se = (float)(dy / d);
-          ang = (float)atan2(dy, dx);
+  for (int k = N - 1; k > 0; --k) {
+    const StrokeRec g = rec[k & 1];
+    const Leaf lf = uniform_leaf(g);
+    for (int i = threadIdx.x; i < k; i += kCompThreadsK) {
+      int nb = 0;
+      for (int q = 0; q < np; ++q) {
+        double2 v = pts[np * i + q];
+        const Chart c = chart(v.x, v.y, g);
+        const bool inside = c.sig <= g.r;
+        nb += inside ? 1 : 0;
+        if (!(inside && skip)) {
+          advance(v.x, v.y, c, displace(c, g, true, lf), g);
+          pts[np * i + q] = v;
         }
-      } else {
-        mx = a.x + (double)(0.5f * len * ce);
-        my = a.y + (double)(0.5f * len * se);
       }
-      ocx[k] = (float)mx;
-      ocy[k] = (float)my;
-      oangle[k] = ang;
-      olength[k] = len;
-      StrokeRec g{};
-      const float ell = fabsf(len), r = p.half_width[k];
-      g.mx = mx;
-      g.my = my;
-      g.ce = ce;
-      g.se = se;
-      g.ell = ell;
-      g.hl = 0.5f * ell;
-      g.two_ell = ell + ell;
-      g.r = r;
-      g.ar = r * fmaf(kPi, r, ell + ell);
-      g.per_r = fmaf(kTwoPi, r, ell + ell);
-      g.floor_c = (eps * r) * (eps * r);
-      rec = g;
-    }
-    __syncthreads();
-    if (k > 0) {
-      const StrokeRec g = rec;
-      const Leaf lf = uniform_leaf(g);
-      for (int i = threadIdx.x; i < k; i += kCompThreadsK) {
-        int nb = 0;
-        for (int q = 0; q < np; ++q) {
-          double2 v = pts[np * i + q];
-          const Chart c = chart(v.x, v.y, g);
-          const bool inside = c.sig <= g.r;
-          nb += inside ? 1 : 0;
-          if (!(inside && skip)) {
-            advance(v.x, v.y, c, displace(c, g, true, lf), g);
-            pts[np * i + q] = v;
-          }
-        }
-        if (nb) blocked[i] += nb;
-      }
+      if (nb) blocked[i] += nb;
+      // stroke k-1 has now met every later stroke: build its record
+      if (i == k - 1) comp_record(p, eps, endpoint, i, pts, ocx, ocy, oangle, olength, rec[i & 1]);
     }
     __syncthreads();
   }

@@ -81,3 +81,18 @@ def test_forward_deterministic():
     a = api.render(dp, opts, "both")
     b = api.render(dp, opts, "both")
     assert torch.equal(a["rgb"], b["rgb"]) and torch.equal(a["owner"], b["owner"])
+
+
+def test_program_value_checks():
+    """The Python layer checks the values the library does not read on the
+    host: finite arrays, positive half-widths, palette in [0, 1]."""
+    require_gpu()
+    good = api.to_device(synth.make_program(20, 4, 5))
+    api.validate_program(good)
+    for field, value in (("half_width", 0.0), ("cx", float("nan")), ("palette", 1.5)):
+        bad = {k: v.clone() for k, v in good.items()}
+        bad[field].view(-1)[0] = value
+        with pytest.raises(ValueError):
+            api.validate_program(bad)
+        with pytest.raises(ValueError):
+            api.FitState(bad, api.Opts(32, 32))
