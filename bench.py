@@ -165,6 +165,52 @@ def api_forms(w, prog, opts, target, iters=20, warm=5):
     return out
 
 
+def transports_benchmark(w, prog, target, reps=5):
+    """The benchmark program under each transport the library implements:
+    the capsule map, its calibrated coupling (per-stroke c_k ~ U(-0.15,
+    0.15)), the inert-mark model R_U and the sixteen-drop R_D. Soft and hard
+    render time (median of reps, HIP events), and for the first three the
+    fused fit step (tbr_fit_step), pixel-strokes per second."""
+    import torch
+    from paper_2609_08722_amd import api, synth
+    dp = api.to_device(prog)
+    P, N = w.pixels, w.n_strokes
+    coup = torch.from_numpy(synth.coupling_coeffs(N, 7)).cuda()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+    out = {}
+    for name, kw in (("capsule", {}), ("coupled", {"coupling": coup}),
+                     ("inert", {"transport": "inert"}), ("drops16", {"transport": "drops16"})):
+        o = api.Opts(w.width, w.height, tau=w.tau, tau_c=w.tau_c, eps=w.eps, ckpt=w.ckpt,
+                     side_slots=23, **kw)
+        r = {"soft_ms": timed(lambda: api.render(dp, o, "soft")),
+             "hard_ms": timed(lambda: api.render(dp, o, "hard"))}
+        if name != "drops16":
+            fit = api.FitState({f: v.clone() for f, v in dp.items()}, o,
+                               api.Adam(r_lo=0.002, r_hi=0.02, l_max=0.08))
+            for _ in range(2):
+                fit.step_checked(target, headroom=8)
+            r["fit_step_ms"] = timed(lambda: fit.step(target))
+            r["fit_pixel_strokes_per_s"] = P * N / (r["fit_step_ms"] * 1e-3)
+            del fit
+        r["soft_pixel_strokes_per_s"] = P * N / (r["soft_ms"] * 1e-3)
+        out[name] = r
+        torch.cuda.empty_cache()
+    return out
+
+
 def compensation_benchmark(w, prog, reps=5):
     """The closed-form compensation pass over the 2000-stroke program (as an
     inert-mark program): 1,999,000 anchor / 3,998,000 endpoint point maps in
@@ -373,6 +419,8 @@ def main():
                     help="skip the 240-step fitting loop")
     ap.add_argument("--no-compensation", action="store_true",
                     help="skip the closed-form compensation pass")
+    ap.add_argument("--no-transports", action="store_true",
+                    help="skip the renders and fit steps under the other transports")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="length of the Poisson serving replay (0 = skip)")
     ap.add_argument("--serve-warmup", type=float, default=1.0,
@@ -580,6 +628,9 @@ def main():
     if not args.no_batched_fit:
         out["batched_fit"] = batched_fit_benchmark()
         log(f"[bench] batched fit: {out['batched_fit']}")
+    if not args.no_transports:
+        out["transports"] = transports_benchmark(w, prog, target)
+        log(f"[bench] transports: {out['transports']}")
     if not args.no_compensation:
         out["compensation"] = compensation_benchmark(w, prog)
         log(f"[bench] compensation: {out['compensation']}")

@@ -129,7 +129,7 @@ BackLayout back_layout(const tbr_render_opts* o, int n, int k) {
 struct FitLayout {
   RenderLayout r;
   BackLayout b;
-  size_t base_r, base_b, loss_part, grads, cursor, total;
+  size_t base_r, base_b, loss_part, grads, cursor, seed, total;
 };
 
 size_t packed_len(int n, int k) { return (size_t)5 * n + (size_t)n * k + (size_t)3 * k; }
@@ -149,6 +149,10 @@ FitLayout fit_layout(const tbr_render_opts* o, int n, int k) {
   off = align_up(off + packed_len(n, k) * sizeof(float));
   L.cursor = off;  // work cursor of the fused launch (single-job step)
   off = align_up(off + sizeof(int));
+  if (o->transport == TBR_TRANSPORT_INERT) {  // dL/dR between the two kernels (no fused launch)
+    L.seed = off;
+    off = align_up(off + n_pixels(o) * 3 * sizeof(float));
+  }
   L.total = off;
   return L;
 }
@@ -363,6 +367,28 @@ tbr_status fit_core(int32_t n_strokes, int32_t n_palette, float* params, float* 
   float4* coup = coup_of(rws, FL.r, opts);
   if ((s = launch_prep(&prog, opts, recs, t.status, coup, st))) return s;
   float* lpart = reinterpret_cast<float*>(ws + FL.loss_part);
+  if (opts->transport == TBR_TRANSPORT_INERT) {
+    // R_U's per-stroke work is too light to hide memory latency at the
+    // fused kernel's occupancy: the soft trace with tape and L2 seed, then
+    // the replay, as two launches (same per-pixel code, same sums)
+    float* grad_rgb = reinterpret_cast<float*>(ws + FL.seed);
+    dim3 grid(tiles_x(opts), tiles_y(opts));
+    k_trace_soft<kInert><<<grid, 256, 0, st>>>(recs, nullptr, N, opts->width, opts->height,
+                                               prog.palette, nullptr, t,
+                                               KSeed{target_rgb, grad_rgb, lpart});
+    if ((s = check_launch("trace_soft"))) return s;
+    k_replay<kInert><<<grid, 256, 0, st>>>(recs, nullptr, N, opts->width, opts->height,
+                                           prog.palette, grad_rgb, t,
+                                           reinterpret_cast<float*>(bws + FL.b.partial));
+    if ((s = check_launch("replay"))) return s;
+    k_loss_final<<<1, 256, 0, st>>>(lpart, (int)n_tiles(opts),
+                                    1.0f / (3.0f * (float)n_pixels(opts)), loss);
+    if ((s = check_launch("loss_final"))) return s;
+    if ((s = launch_reduce(&prog, opts, &pg, bws, FL.b, st))) return s;
+    *g_out = g;
+    *records = t.status;
+    return TBR_OK;
+  }
   // soft forward with tape, L2 seed and replay adjoint of each tile in one
   // persistent launch (one drain of the GPU per step instead of two)
   FitJobsK KJ{};

@@ -294,23 +294,22 @@ __device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, boo
 // A_l(r), at the centres of K equal pieces of the segment, laid from its -e
 // end; the backward map undoes the last drop first. A drop at c takes the
 // point at distance rho from c to distance rho' = sqrt(rho^2 - s^2) on the
-// same ray, floored at pi (rho'^2) >= (eps s)^2. Each drop's map is
-// singular on its circle rho = s, and sixteen such circles lie around every
-// stroke, so the point's offset from each drop centre is formed in FP64 and
-// each drop's FP32 displacement (rho' / rho - 1) (p - c), written as
-// (rho'^2 - rho^2) / (rho^2 (1 + rho' / rho)) (p - c) without cancellation,
-// is added to the FP64 offset at once.
+// same ray, floored at pi (rho'^2) >= (eps s)^2. The drops work on the FP32
+// offset from the stroke centre, rounded once, and accumulate their small
+// displacements, which are then added to the FP64 state: rho' / rho - 1 =
+// (rho'^2 - rho^2) / (rho^2 (1 + rho' / rho)) has no cancellation.
 constexpr int kNumDrops = 16;
 __device__ __forceinline__ void drops_backward(double& x, double& y, const StrokeRec& g) {
   const float s2 = g.ar * (1.f / (kNumDrops * kPi));
   // eps^2 = floor_c / r^2, so the floor on rho'^2 is floor_c s^2 / (pi r^2)
   const float fl = g.r > 0.f ? g.floor_c * rcp(g.r * g.r) * (s2 * (1.f / kPi)) : 0.f;
-  const double ux = (double)(g.ell * g.ce), uy = (double)(g.ell * g.se);  // -e end to +e end
-  double ox = x - g.mx, oy = y - g.my;
+  const float ux = g.ell * g.ce, uy = g.ell * g.se;  // the segment, -e end to +e end
+  const float d0x = (float)(x - g.mx), d0y = (float)(y - g.my);
+  float Dx = 0.f, Dy = 0.f;
 #pragma unroll
   for (int j = kNumDrops - 1; j >= 0; --j) {
-    const double f = ((double)j + 0.5) * (1.0 / kNumDrops) - 0.5;
-    const float px = (float)fma(-f, ux, ox), py = (float)fma(-f, uy, oy);
+    const float f = ((float)j + 0.5f) * (1.f / kNumDrops) - 0.5f;
+    const float px = fmaf(-f, ux, d0x) + Dx, py = fmaf(-f, uy, d0y) + Dy;
     const float rho2 = fmaf(px, px, py * py);
     const float cq = rho2 - s2;
     const bool floored = cq < fl;
@@ -318,11 +317,11 @@ __device__ __forceinline__ void drops_backward(double& x, double& y, const Strok
     const float inv = rho2 > 0.f ? rcp(rho2) : 0.f;
     const float k = hw_sqrt((floored ? fl : cq) * inv);
     const float sc = num * inv * rcp(1.f + k);
-    ox += (double)(px * sc);
-    oy += (double)(py * sc);
+    Dx = fmaf(px, sc, Dx);
+    Dy = fmaf(py, sc, Dy);
   }
-  x = g.mx + ox;
-  y = g.my + oy;
+  x += (double)Dx;
+  y += (double)Dy;
 }
 
 // Apply a displacement (a, b) along (e, n), unfolded, to the FP64 state.
