@@ -43,7 +43,7 @@ FLOPS_REPLAY = 291   # replay step: chart, Phi displacement, advance, VJP, wave 
 # HBM bytes per k_fit_fused launch at the bench workload, from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
 # in the same runs; valid only for the kernel sources it was measured on.
-TRAFFIC = {"sha": "9c1ffadbc2b35662", "bytes": 359.8e6 + 588.3e6}
+TRAFFIC = {"sha": "c4b755afb71c34ec", "bytes": 359.2e6 + 588.3e6}
 
 
 def kernel_sha():
