@@ -31,6 +31,13 @@ constexpr float kHalfPi = 1.57079632679489661923f;
 constexpr float kLog2e = 1.44269504088896340736f;
 // alpha = e^z / (1 + e^z) <= 1 - 1e-7   <=>   e^z <= (1 - 1e-7) / 1e-7
 constexpr float kEzMax = 9999999.0f;
+// Coverage below sigmoid(-28) = 7e-13 is skipped for a whole wave: 1 - alpha
+// then rounds to exactly 1.0f, so transmittance is unchanged bitwise and every
+// dropped colour / gradient term is below 2^-40 of the terms kept.
+constexpr float kFarZ = -28.f;
+// Smallest normal FP32 number: the floor of a reciprocal's argument where the
+// argument is 0 only together with the factor it multiplies.
+constexpr float kMinNormal = 1.17549435e-38f;
 
 // Per-stroke constants, prepared once per launch (80 bytes, 20 words).
 // Wave-uniform values are precomputed here: the vector ALU would otherwise
@@ -44,7 +51,7 @@ struct __align__(16) StrokeRec {
   float per_r;      // Steiner perimeter P_l(r) = 2 l + 2 pi r
   float inv_wd;     // 1 / max(tau r, tau_min)
   float floor_c;    // (eps r)^2
-  float dfloor_dr;  // d (eps r)^2 / dr = 2 eps^2 r
+  float far_sig;    // r + 28 wd: beyond it the coverage is below sigmoid(-28)
   float dwd_dr;     // d max(tau r, tau_min) / dr: tau or 0
   float cr, cg, cb; // colour c_i = softmax(z_i / tau_c) P (or P[argmax])
   int label;        // argmax_k z_ik (hard colour index)
@@ -81,7 +88,8 @@ __device__ __forceinline__ float atan01(float a) {
 // atan2(y, x) for y, x >= 0 (first quadrant); 0 at the origin.
 __device__ __forceinline__ float atan2_q1(float y, float x) {
   float hi = fmaxf(x, y), lo = fminf(x, y);
-  float a = hi > 0.f ? lo * rcp(hi) : 0.f;
+  // at the origin lo = 0, so the floored reciprocal gives a = 0
+  float a = lo * rcp(fmaxf(hi, kMinNormal));
   float t = atan01(a);
   return y > x ? kHalfPi - t : t;
 }
@@ -99,7 +107,9 @@ struct Chart {
   float sig;       // distance to the segment
   float th;        // cap angle measured from the normal; 0 on the flank
   float sn, cs;    // sin / cos of th (E / sig, H / sig)
+  float inv_sig;   // 1 / sigma, floored on the segment
   float per;       // P_l(sigma)
+  float inv_per;   // 1 / P_l(sigma), floored at the drop centre (where t = 0)
   float w;         // arclength fraction from the flank midpoint, [0, 1/4]
 };
 
@@ -115,12 +125,14 @@ __device__ __forceinline__ Chart chart(double x, double y, const StrokeRec& g) {
   c.E = fmaxf(c.S - g.hl, 0.f);
   c.sig = hw_sqrt(fmaf(c.H, c.H, c.E * c.E));
   c.th = atan2_q1(c.E, c.H);
-  float inv_sig = c.sig > 0.f ? rcp(c.sig) : 0.f;
-  c.sn = c.E * inv_sig;
-  c.cs = c.sig > 0.f ? c.H * inv_sig : 1.f;
+  // on the segment E = 0, so the floored reciprocal gives sin th = 0
+  c.inv_sig = rcp(fmaxf(c.sig, kMinNormal));
+  c.sn = c.E * c.inv_sig;
+  c.cs = c.sig > 0.f ? c.H * c.inv_sig : 1.f;
   float t = fmaf(c.sig, c.th, fminf(c.S, g.hl));  // arclength from the flank midpoint
   c.per = fmaf(kTwoPi, c.sig, g.two_ell);          // P_l(sigma)
-  c.w = c.per > 0.f ? t * rcp(c.per) : 0.f;        // drop centre: w := 0
+  c.inv_per = rcp(fmaxf(c.per, kMinNormal));
+  c.w = t * c.inv_per;                               // drop centre: t = 0, w = 0
   return c;
 }
 
@@ -209,6 +221,23 @@ __device__ __forceinline__ Leaf coupled_leaf(float w, const StrokeRec& g, const 
   return lf;
 }
 
+// A lane whose coverage z = (edge - sigma) / wd is below kFarZ. Uniform
+// insertion compares sigma with the stroke's precomputed r + 28 wd (one
+// compare); a coupled leaf's edge varies along the stroke.
+template <bool kC>
+__device__ __forceinline__ bool is_far(float sig, const Leaf& lf, const StrokeRec& g) {
+  if constexpr (kC) {
+    return sig - lf.r > g.far_sig - g.r;
+  } else {
+    return sig > g.far_sig;
+  }
+}
+
+// d (eps r)^2 / dr = 2 eps^2 r = 2 (eps r)^2 / r (used where the floor binds).
+__device__ __forceinline__ float dfloor_dr(const StrokeRec& g) {
+  return g.r > 0.f ? 2.f * g.floor_c * rcp(g.r) : 0.f;
+}
+
 // Backward numerator C = A(sigma') - A(rl), factored (Eq. back).
 __device__ __forceinline__ float back_area(float sig, const Leaf& lf, float two_ell) {
   return (sig - lf.r) * fmaf(kPi, sig + lf.r, two_ell);
@@ -270,7 +299,7 @@ __device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, boo
   float th_o = fminf(fmaxf(t_o - g.hl, 0.f) * inv_sig_o, kHalfPi);
   const bool cap_in = c.th > 0.f, cap_out = th_o > 0.f;
   // 1 / P_l(sig) is the chart's reciprocal (it also gives w)
-  float dth_cc = dsig * g.ell * (kPi - 2.f * c.th) * (rcp(c.per) * inv_sig_o);
+  float dth_cc = dsig * g.ell * (kPi - 2.f * c.th) * (c.inv_per * inv_sig_o);
   float dth = (cap_in && cap_out) ? dth_cc : th_o - c.th;
   float sd, cdm1;
   if (wave_all(fabsf(dth) < kSmallTurn)) {
@@ -388,6 +417,7 @@ struct VjpIn {
   // output point x_{i-1}
   float so, ho;          // signed local coordinates
   float rho;             // distance of x_{i-1}
+  float inv_rho, inv_p0; // 1 / rho and 1 / P_l(rho)
   float th_o, sn_o, cs_o;
   bool floored;          // the floor C >= (eps r)^2 bound at x_i
   // coverage at x_i
@@ -442,7 +472,7 @@ __device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, f
   o.gmy = ly;
   o.gphi = fmaf(v.so, gn, -(v.ho * ge));
   // S' = min(t', l/2) + rho sin th', H' = rho cos th', th' = (t' - l/2) / rho
-  float inv_rho = rcp(v.rho);
+  const float inv_rho = v.inv_rho;
   float thb = v.rho * fmaf(sbp, v.cs_o, -(hbp * v.sn_o));
   float tpb = thb * inv_rho;
   float rhob = fmaf(sbp, v.sn_o, hbp * v.cs_o) - tpb * v.th_o;
@@ -453,7 +483,7 @@ __device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, f
   rhob = fmaf(kTwoPi * v.w, tpb, rhob);
   float ellb = 2.f * v.w * tpb;
   // rho = A_l^{-1}(C): dC = P_l(rho) drho + 2 rho dl
-  float cb = rhob * rcp(p0);
+  float cb = rhob * v.inv_p0;
   ellb = fmaf(-2.f * v.rho, cb, ellb);
   // C = A_l(sigma') - A_l(r), or the floor (eps r)^2
   float p1 = fmaf(kTwoPi, v.sig, two_ell);
@@ -461,7 +491,7 @@ __device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, f
   float sigb = v.floored ? 0.f : cb * p1;
   if constexpr (kCoupled) {
     // C = A_l(sigma') - G
-    o.gr = v.floored ? cb * g.dfloor_dr : -(cb * pr * lf.g);
+    o.gr = v.floored ? cb * dfloor_dr(g) : -(cb * pr * lf.g);
     ellb = v.floored ? ellb : fmaf(2.f * fmaf(-g.r, lf.g, v.sig), cb, ellb);
     wb = v.floored ? wb : fmaf(-cb * g.ar, lf.dg, wb);
     // coverage z = (rl - sigma') / wd, before w's adjoint is passed on
@@ -475,7 +505,7 @@ __device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, f
       wb = fmaf(rlb * g.ar, lf.dg, wb);
     }
   } else {
-    o.gr = v.floored ? cb * g.dfloor_dr : -(cb * pr);
+    o.gr = v.floored ? cb * dfloor_dr(g) : -(cb * pr);
     ellb = v.floored ? ellb : fmaf(2.f * (v.sig - g.r), cb, ellb);
   }
   // w = t / P_l(sigma')

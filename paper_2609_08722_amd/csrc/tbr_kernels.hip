@@ -45,7 +45,7 @@ __device__ __forceinline__ StrokeRec prep_stroke(const KProgram& p, const KOpts&
   g.dwd_dr = rel ? o.tau : 0.f;
   float er = o.eps * r;
   g.floor_c = er * er;
-  g.dfloor_dr = 2.f * o.eps * er;
+  g.far_sig = fmaf(-kFarZ, wd, r);
   // colour: softmax(z / tau_c) P, or P[argmax z] when tau_c == 0
   const float* z = p.logits + (size_t)i * p.k;
   int best = 0;
@@ -105,10 +105,6 @@ __global__ void __launch_bounds__(256) k_serve_prep(const ServePrep* __restrict_
   if (b >= q.block0 && i < q.prog.n) q.out[i] = prep_stroke(q.prog, q.opts, i);
 }
 
-// Coverage below sigmoid(-28) = 7e-13 is skipped for a whole wave: 1 - alpha
-// then rounds to exactly 1.0f, so transmittance is unchanged bitwise and every
-// dropped colour / gradient term is below 2^-40 of the terms kept.
-constexpr float kFarZ = -28.f;
 
 // Wave-uniform load of a stroke record (the index is uniform, so the
 // compiler issues scalar loads).
@@ -196,7 +192,7 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
     // are unchanged to FP32 rounding. Lanes past a ragged canvas edge trace
     // a point just outside the canvas and vote too: that can only keep the
     // exact path.
-    if (!wave_all((lf.r - c.sig) * g.inv_wd < kFarZ)) {
+    if (!wave_all(is_far<kT == kCoupled>(c.sig, lf, g))) {
       Cover v = cover(c.sig, g, lf.r);
       float t = trans_value(tm, te);
       float ta = t * v.alpha;
@@ -538,7 +534,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           tm = ckt.x;
           te = (int)ckt.y;
         }
-        if (!wave_all((g.r - ca.sig) * g.inv_wd < kFarZ)) {
+        if (!wave_all(is_far<false>(ca.sig, uniform_leaf(g), g))) {
           Cover cv = cover(ca.sig, g, g.r);
           if (!ck) {
             tm *= cv.inv_q;
@@ -546,9 +542,10 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           }
           float t = trans_value(tm, te);
           float lc = fmaf(lcr, g.cr, fmaf(lcg, g.cg, lcb * g.cb));
-          float mu = t * (lc - lt);
+          const float dlt = lc - lt;
+          float mu = t * dlt;
           float ta = t * cv.alpha;
-          lt = fmaf(cv.q, lt, cv.alpha * lc);
+          lt = fmaf(cv.alpha, dlt, lt);  // (1 - alpha) lt + alpha lc
           VjpOut vo = vjp_cover_only(ca, g, cv, mu);
           float v[8] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
           tot = row_sums8(v, lane);
@@ -572,15 +569,18 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
   for (int c0 = 0; c0 < n; c0 += kChunk) {
     const int buf = (c0 / kChunk) & 1;
     const int cn = min(kChunk, n - c0);
-    for (int j = 0; j < cn; ++j) {
-      const int i = c0 + j;  // stroke index (0-based); its input state is x_{i+1}
-      const StrokeRec g = load_rec(recs, i);
-      const bool ck = i == next_ck;
-      if (ck) next_ck = next_ck + k + 1 < n ? next_ck + k : 0x7fffffff;
-      const bool pop = top_idx == i;
-      float tot;
-      if (!ck && !wave_any(pop)) {
-        // Common case: every lane regenerates x_i = Phi_i(x_{i-1}) (Eq. rpos).
+    int j = 0;
+    while (j < cn) {
+      // Common steps, up to the next one where some lane loads its state:
+      // every lane regenerates x_i = Phi_i(x_{i-1}) (Eq. rpos). Keeping
+      // these in a loop of their own, with the rare loading step after it,
+      // lets the loop-carried state stay in place (no register copies where
+      // the paths join).
+      for (; j < cn; ++j) {
+        const int i = c0 + j;  // stroke index (0-based); its input state is x_{i+1}
+        if (i == next_ck || wave_any(top_idx == i)) break;
+        const StrokeRec g = load_rec(recs, i);
+        float tot;
         Chart ca = chart(x, y, g);
         const Leaf lf = leaf_at<kC>(ca, g, coup, i);
         Move mv = displace<true>(ca, g, false, lf);
@@ -602,11 +602,13 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
         vi.so = ca.s;
         vi.ho = ca.h;
         vi.rho = ca.sig;
+        vi.inv_rho = ca.inv_sig;
+        vi.inv_p0 = ca.inv_per;
         vi.th_o = ca.th;
         vi.sn_o = ca.sn;
         vi.cs_o = ca.cs;
         step_by(x, y, da, db, g);
-        if (wave_all((lf.r - vi.sig) * g.inv_wd < kFarZ)) {
+        if (wave_all(is_far<kC>(vi.sig, lf, g))) {
           // far stroke: alpha, mu dalpha and the colour terms vanish to FP32
           vi.z = 0.f;
           vi.alpha = 0.f;
@@ -627,23 +629,33 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           renorm(tm, te);
           float t = trans_value(tm, te);
           float lc = fmaf(lcr, g.cr, fmaf(lcg, g.cg, lcb * g.cb));
-          float mu = t * (lc - lt);
+          const float dlt = lc - lt;
+          float mu = t * dlt;
           float ta = t * cv.alpha;
-          lt = fmaf(cv.q, lt, cv.alpha * lc);
+          lt = fmaf(cv.alpha, dlt, lt);  // (1 - alpha) lt + alpha lc
           VjpOut vo = vjp_step<true, kC>(vi, g, lx, ly, mu, lf);
           lx = vo.gx;
           ly = vo.gy;
           float v[8] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
           tot = row_sums8(v, lane);
         }
-      } else {
-        // Some lane takes x_i from the side table (the floor bound there in
-        // the forward pass) or the step is a checkpoint (drift reset).
-        double ax = x, ay = y;
+        if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
+      }
+      if (j == cn) break;
+      {
+        // The loading step: some lane takes x_i from the side table (the
+        // floor bound there in the forward pass), or the step is a
+        // checkpoint (drift reset).
+        const int i = c0 + j;
+        const StrokeRec g = load_rec(recs, i);
+        const bool ck = i == next_ck;
+        if (ck) next_ck = next_ck + k + 1 < n ? next_ck + k : 0x7fffffff;
+        const bool pop = top_idx == i;
+        float tot;
         if (pop) {
           double2 r = tape.side_xy[(size_t)(top - 1) * P + id.p];
-          ax = r.x;
-          ay = r.y;
+          x = r.x;
+          y = r.y;
           --top;
           top_idx = top > 0 ? tape.side_idx[(size_t)(top - 1) * P + id.p] : -1;
         }
@@ -651,15 +663,15 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
         if (ck && id.active) {
           double2 r = tape.ckpt_xy[(size_t)((i + 1) / k) * P + id.p];
           ckt = tape.ckpt_t[(size_t)((i + 1) / k) * P + id.p];
-          ax = r.x;
-          ay = r.y;
+          x = r.x;
+          y = r.y;
         }
         const bool loaded = pop || ck;
         // One chart and one displacement serve both directions: for a
         // regenerated lane the chart is at x_{i-1} and Phi_i gives x_i;
         // for a loaded lane the chart is at x_i and psi_i gives the
         // (discarded) x_{i-1}, whose geometry the adjoint needs.
-        Chart ca = chart(ax, ay, g);
+        Chart ca = chart(x, y, g);
         const Leaf lf = leaf_at<kC>(ca, g, coup, i);
         Move mv = displace<true>(ca, g, loaded, lf);
         const float da = ca.sgs * mv.dS, db = ca.sgh * mv.dH;
@@ -680,11 +692,11 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           vi.so = sn_pt;
           vi.ho = hn_pt;
           vi.rho = mv.sig_o;
+          vi.inv_rho = rcp(mv.sig_o);
+          vi.inv_p0 = rcp(fmaf(kTwoPi, mv.sig_o, g.two_ell));
           vi.th_o = mv.th_o;
           vi.sn_o = mv.sn_o;
           vi.cs_o = mv.cs_o;
-          x = ax;
-          y = ay;
         } else {  // in = regenerated x_i, out = chart point x_{i-1}
           vi.s = sn_pt;
           vi.h = hn_pt;
@@ -696,6 +708,8 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           vi.so = ca.s;
           vi.ho = ca.h;
           vi.rho = ca.sig;
+          vi.inv_rho = ca.inv_sig;
+          vi.inv_p0 = ca.inv_per;
           vi.th_o = ca.th;
           vi.sn_o = ca.sn;
           vi.cs_o = ca.cs;
@@ -715,16 +729,18 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
         }
         float t = trans_value(tm, te);
         float lc = fmaf(lcr, g.cr, fmaf(lcg, g.cg, lcb * g.cb));
-        float mu = t * (lc - lt);
+        const float dlt = lc - lt;
+        float mu = t * dlt;
         float ta = t * cv.alpha;
-        lt = fmaf(cv.q, lt, cv.alpha * lc);
+        lt = fmaf(cv.alpha, dlt, lt);  // (1 - alpha) lt + alpha lc
         VjpOut vo = vjp_step<true, kC>(vi, g, lx, ly, mu, lf);
         lx = vo.gx;
         ly = vo.gy;
         float v[8] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
         tot = row_sums8(v, lane);
+        if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
+        ++j;
       }
-      if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
     }
     __syncthreads();
     {
