@@ -571,18 +571,26 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
     const int cn = min(kChunk, n - c0);
     int j = 0;
     while (j < cn) {
-      // Common steps, up to the next one where some lane loads its state:
-      // every lane regenerates x_i = Phi_i(x_{i-1}) (Eq. rpos). Keeping
-      // these in a loop of their own, with the rare loading step after it,
-      // lets the loop-carried state stay in place (no register copies where
-      // the paths join).
+      // Common steps, far from every lane of the wave, up to the next step
+      // where some lane loads its state or the stroke comes near: every lane
+      // regenerates x_i = Phi_i(x_{i-1}) (Eq. rpos), and alpha, mu dalpha and
+      // the colour terms vanish to FP32. Phi moves a point away from the
+      // stroke, so a wave that is far before the step is far after it and
+      // the vote can come first. Keeping these steps in a loop of their own,
+      // with the general step after it, leaves the loop one path: the state
+      // it carries needs no register copies where paths would join. The
+      // record is read before the exit tests and handed to the general step:
+      // used on both sides of them, all its loads issue at the top of the
+      // step (loads used only after the far vote would issue after it, with
+      // their latency in the way).
+      StrokeRec g;
       for (; j < cn; ++j) {
         const int i = c0 + j;  // stroke index (0-based); its input state is x_{i+1}
+        g = load_rec(recs, i);
         if (i == next_ck || wave_any(top_idx == i)) break;
-        const StrokeRec g = load_rec(recs, i);
-        float tot;
         Chart ca = chart(x, y, g);
         const Leaf lf = leaf_at<kC>(ca, g, coup, i);
+        if (!wave_all(is_far<kC>(ca.sig, lf, g))) break;
         Move mv = displace<true>(ca, g, false, lf);
         // unfolded displacement; the new point's signed coordinates are the
         // chart's plus it (sgs (S + dS) = s + sgs dS, exactly)
@@ -607,47 +615,24 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
         vi.th_o = ca.th;
         vi.sn_o = ca.sn;
         vi.cs_o = ca.cs;
+        vi.z = 0.f;
+        vi.alpha = 0.f;
+        vi.q = 1.f;
+        vi.clamped = true;
         step_by(x, y, da, db, g);
-        if (wave_all(is_far<kC>(vi.sig, lf, g))) {
-          // far stroke: alpha, mu dalpha and the colour terms vanish to FP32
-          vi.z = 0.f;
-          vi.alpha = 0.f;
-          vi.q = 1.f;
-          vi.clamped = true;
-          VjpOut vo = vjp_step<false, kC>(vi, g, lx, ly, 0.f, lf);
-          lx = vo.gx;
-          ly = vo.gy;
-          float v[5] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr};
-          tot = row_sums5(v, lane);
-        } else {
-          Cover cv = cover(vi.sig, g, lf.r);
-          vi.z = cv.z;
-          vi.alpha = cv.alpha;
-          vi.q = cv.q;
-          vi.clamped = cv.clamped;
-          tm *= cv.inv_q;  // T_i = T_{i-1} / (1 - alpha_i)  (Eq. rT)
-          renorm(tm, te);
-          float t = trans_value(tm, te);
-          float lc = fmaf(lcr, g.cr, fmaf(lcg, g.cg, lcb * g.cb));
-          const float dlt = lc - lt;
-          float mu = t * dlt;
-          float ta = t * cv.alpha;
-          lt = fmaf(cv.alpha, dlt, lt);  // (1 - alpha) lt + alpha lc
-          VjpOut vo = vjp_step<true, kC>(vi, g, lx, ly, mu, lf);
-          lx = vo.gx;
-          ly = vo.gy;
-          float v[8] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
-          tot = row_sums8(v, lane);
-        }
+        VjpOut vo = vjp_step<false, kC>(vi, g, lx, ly, 0.f, lf);
+        lx = vo.gx;
+        ly = vo.gy;
+        float v[5] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr};
+        const float tot = row_sums5(v, lane);
         if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
       }
       if (j == cn) break;
       {
-        // The loading step: some lane takes x_i from the side table (the
-        // floor bound there in the forward pass), or the step is a
-        // checkpoint (drift reset).
+        // The general step: the stroke is near some lane of the wave, or
+        // some lane takes x_i from the side table (the floor bound there in
+        // the forward pass), or the step is a checkpoint (drift reset).
         const int i = c0 + j;
-        const StrokeRec g = load_rec(recs, i);
         const bool ck = i == next_ck;
         if (ck) next_ck = next_ck + k + 1 < n ? next_ck + k : 0x7fffffff;
         const bool pop = top_idx == i;
