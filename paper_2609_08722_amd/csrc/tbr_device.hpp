@@ -318,6 +318,54 @@ __device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, boo
   return m;
 }
 
+// Phi of a charted point with 1 / P_l(sig_o), for the replay's common steps:
+// displace<true>(c, g, false, lf) with a uniform branch for a wave whose
+// lanes all lie on the cap. Phi inserts area, so t_o = w P_l(sig_o) > t and
+// a point on a cap stays on it; the cap-to-cap case (that of almost every
+// wave a stroke is far from) needs neither t_o nor the flank terms.
+__device__ __forceinline__ Move regenerate(const Chart& c, const StrokeRec& g, const Leaf& lf) {
+  Move m;
+  const float two_ell = g.two_ell;
+  const float q = fwd_area(c.sig, lf, two_ell);
+  m.floored = false;
+  const float X = fmaf(g.ell, g.ell, kPi * q);
+  const float rs = __builtin_amdgcn_rsqf(X);
+  m.sig_o = q * rcp(g.ell + X * rs);
+  m.inv_per_o = 0.5f * rs;
+  const float dsig = lf.ar * rcp(fmaf(kPi, c.sig + m.sig_o, two_ell));
+  const float inv_sig_o = rcp(m.sig_o);
+  const bool cap_in = c.th > 0.f;
+  const float dth_cc = dsig * g.ell * (kPi - 2.f * c.th) * (c.inv_per * inv_sig_o);
+  float dth, th_o, extra;
+  if (wave_all(cap_in)) {
+    dth = dth_cc;
+    th_o = c.th + dth;
+    extra = 0.f;
+  } else {
+    const float t_o = c.w * fmaf(kTwoPi, m.sig_o, two_ell);
+    const float th_new = fminf(fmaxf(t_o - g.hl, 0.f) * inv_sig_o, kHalfPi);
+    const bool cc = cap_in && th_new > 0.f;
+    dth = cc ? dth_cc : th_new - c.th;
+    th_o = cc ? c.th + dth : th_new;
+    const float dt = kTwoPi * c.w * dsig;
+    extra = cc ? 0.f : dt - dsig * th_new - c.sig * dth;
+  }
+  float sd, cdm1;
+  if (wave_all(fabsf(dth) < kSmallTurn)) {
+    sincosm1_small(dth, sd, cdm1);
+  } else {
+    sincosm1(dth, sd, cdm1);
+  }
+  const float dsin = fmaf(c.sn, cdm1, c.cs * sd);
+  const float dcos = fmaf(c.cs, cdm1, -(c.sn * sd));
+  m.sn_o = c.sn + dsin;
+  m.cs_o = c.cs + dcos;
+  m.th_o = th_o;
+  m.dS = fmaf(dsig, m.sn_o, fmaf(c.sig, dsin, extra));
+  m.dH = fmaf(dsig, m.cs_o, c.sig * dcos);
+  return m;
+}
+
 // The displacement of the renderer R_D (Sec. "Transfer across transport
 // constructions"): K = 16 drop maps (Lu 2012) of radius s, K pi s^2 =
 // A_l(r), at the centres of K equal pieces of the segment, laid from its -e
@@ -472,9 +520,17 @@ __device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, f
   o.gmy = ly;
   o.gphi = fmaf(v.so, gn, -(v.ho * ge));
   // S' = min(t', l/2) + rho sin th', H' = rho cos th', th' = (t' - l/2) / rho
-  const float inv_rho = v.inv_rho;
-  float thb = v.rho * fmaf(sbp, v.cs_o, -(hbp * v.sn_o));
-  float tpb = thb * inv_rho;
+  // th' has adjoint rho (S'b cos th' - H'b sin th'), and t' has it over
+  // rho. A far stroke's output point is at rho > r + 28 wd > 0, where the
+  // factors rho and 1 / rho cancel; elsewhere rho may be 0 (a point on the
+  // segment), where th' is held at 0 and passes nothing on.
+  float tpb;
+  if constexpr (kCover) {
+    const float thb = v.rho * fmaf(sbp, v.cs_o, -(hbp * v.sn_o));
+    tpb = thb * v.inv_rho;
+  } else {
+    tpb = fmaf(sbp, v.cs_o, -(hbp * v.sn_o));
+  }
   float rhob = fmaf(sbp, v.sn_o, hbp * v.cs_o) - tpb * v.th_o;
   float hlb = sbp - tpb;
   // t' = w P_l(rho)

@@ -591,7 +591,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
         Chart ca = chart(x, y, g);
         const Leaf lf = leaf_at<kC>(ca, g, coup, i);
         if (!wave_all(is_far<kC>(ca.sig, lf, g))) break;
-        Move mv = displace<true>(ca, g, false, lf);
+        Move mv = regenerate(ca, g, lf);
         // unfolded displacement; the new point's signed coordinates are the
         // chart's plus it (sgs (S + dS) = s + sgs dS, exactly)
         const float da = ca.sgs * mv.dS, db = ca.sgh * mv.dH;
