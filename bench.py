@@ -31,19 +31,22 @@ if ROOT not in sys.path:
 
 # MI355X published FP32 vector peak: 256 CUs x 2.4 GHz x 256 FLOP/clock/CU.
 PEAK_FP32_FLOPS = 157.3e12
-# Algorithmic FP operations per pixel-stroke, counted from the formulas of
-# each phase (FMA = 2, every other FP32/FP64 operation incl. compare, select,
-# min/max, conversion and transcendental = 1). These are the counts of a
-# stroke far from the pixel (coverage below
-# 7e-13, no coverage or colour terms), the case of >99% of pixel-strokes here;
-# a near stroke needs 20 (forward) / 41 (replay) more. The path is ALU-bound:
-# HBM traffic is ~0.3 B per pixel-stroke.
-FLOPS_FWD = 163      # soft forward step with tape: chart, psi displacement, advance
-FLOPS_REPLAY = 291   # replay step: chart, Phi displacement, advance, VJP, wave reduction
+# Algorithmic FP operations per pixel-stroke, counted item by item from the
+# formulas the kernels evaluate (FMA = 2; every other FP32/FP64 operation,
+# incl. abs, compare, select, min/max, conversion and transcendental, = 1;
+# a sign folded into an operand = 0). These are the counts of a stroke far
+# from the wave (coverage below 7e-13: no coverage or colour terms), >99% of
+# pixel-strokes here, whose rotation is small and, in the replay, whose wave
+# lies on the stroke's cap (the common case); other steps do more work, so
+# the counts are a lower bound. The path is ALU-bound: HBM traffic is
+# ~0.45 B per pixel-stroke.
+FLOPS_FWD = 154      # soft forward step: chart 62, far vote 1, psi 79, advance 12
+FLOPS_REPLAY = 223   # replay step: chart 62, vote 1, Phi 54, new point 4, advance 10,
+                     # VJP 73, wave reduction 19
 # HBM bytes per k_fit_fused launch at the bench workload, from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
 # in the same runs; valid only for the kernel sources it was measured on.
-TRAFFIC = {"sha": "c4b755afb71c34ec", "bytes": 359.2e6 + 588.3e6}
+TRAFFIC = {"sha": "c0531097fbf840bb", "bytes": 350.6e6 + 576.0e6}
 
 
 def kernel_sha():
