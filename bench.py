@@ -41,8 +41,8 @@ PEAK_FP32_FLOPS = 157.3e12
 # the counts are a lower bound. The path is ALU-bound: HBM traffic is
 # ~0.45 B per pixel-stroke.
 FLOPS_FWD = 154      # soft forward step: chart 62, far vote 1, psi 79, advance 12
-FLOPS_REPLAY = 223   # replay step: chart 62, vote 1, Phi 54, new point 4, advance 10,
-                     # VJP 73, wave reduction 19
+FLOPS_REPLAY = 213   # replay step: chart 62, vote 1, Phi 54, new point 4, advance 10,
+                     # VJP 63, wave reduction 19
 # HBM bytes per k_fit_fused launch at the bench workload, from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
 # in the same runs; valid only for the kernel sources it was measured on.

@@ -598,4 +598,42 @@ __device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, f
   return o;
 }
 
+// vjp_step<false> for the replay's common step under uniform insertion: the
+// stroke is far from the wave (no coverage terms), no lane is floored, and
+// the input point x_i is the regenerated one, at sigma' > rho > 0. The same
+// adjoint with its terms gathered: the rho and 1 / rho of th' cancel, the
+// th' and 2 pi w terms of rho's and sigma''s adjoints share one factor each,
+// and the four terms of l's adjoint collapse to
+// 2 (w (t'b - tb) + (sigma' - rho - r) Cb).
+__device__ __forceinline__ VjpOut vjp_far(const VjpIn& v, const StrokeRec& g, float lx, float ly) {
+  VjpOut o;
+  const float two_ell = g.two_ell;
+  const float ge = fmaf(lx, g.ce, ly * g.se);
+  const float gn = fmaf(ly, g.ce, -(lx * g.se));
+  const float sbp = v.sgs * ge;  // adjoint of S'
+  const float hbp = v.sgh * gn;  // adjoint of H'
+  const float gphi0 = fmaf(v.so, gn, -(v.ho * ge));
+  const float tpb = fmaf(sbp, v.cs_o, -(hbp * v.sn_o));  // adjoint of t'
+  const float tw = kTwoPi * v.w;
+  // rho: S' and H' directly, th' = (t' - l/2) / rho, and t' = w P_l(rho)
+  const float rhob = fmaf(tpb, tw - v.th_o, fmaf(sbp, v.sn_o, hbp * v.cs_o));
+  const float cb = rhob * v.inv_p0;  // rho = A_l^{-1}(C)
+  // w = t / P_l(sigma') receives t' P_l(rho); t passes it on
+  const float tb = tpb * (fmaf(kTwoPi, v.rho, two_ell) * v.inv_p1);
+  const float sigb = fmaf(v.th - tw, tb, cb * fmaf(kTwoPi, v.sig, two_ell));
+  o.gr = -(cb * g.per_r);
+  const float ellh = fmaf(v.w, tpb - tb, ((v.sig - v.rho) - g.r) * cb);
+  const float eb = fmaf(sigb, v.sn, tb * v.cs);
+  const float hb = fmaf(sigb, v.cs, -(tb * v.sn));
+  const float hlb = (sbp - tpb + tb) - eb;
+  const float ssb = v.sgs * eb, shb = v.sgh * hb;
+  o.gx = fmaf(ssb, g.ce, -(shb * g.se));
+  o.gy = fmaf(ssb, g.se, shb * g.ce);
+  o.gmx = lx - o.gx;
+  o.gmy = ly - o.gy;
+  o.gphi = fmaf(ssb, v.h, fmaf(-shb, v.s, gphi0));
+  o.gell = fmaf(2.f, ellh, 0.5f * hlb);
+  return o;
+}
+
 }  // namespace tbr

@@ -620,7 +620,12 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
         vi.q = 1.f;
         vi.clamped = true;
         step_by(x, y, da, db, g);
-        VjpOut vo = vjp_step<false, kC>(vi, g, lx, ly, 0.f, lf);
+        VjpOut vo;
+        if constexpr (kC) {
+          vo = vjp_step<false, true>(vi, g, lx, ly, 0.f, lf);
+        } else {
+          vo = vjp_far(vi, g, lx, ly);
+        }
         lx = vo.gx;
         ly = vo.gy;
         float v[5] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr};
