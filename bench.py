@@ -40,7 +40,7 @@ PEAK_FP32_FLOPS = 157.3e12
 # lies on the stroke's cap (the common case); other steps do more work, so
 # the counts are a lower bound. The path is ALU-bound: HBM traffic is
 # ~0.45 B per pixel-stroke.
-FLOPS_FWD = 154      # soft forward step: chart 62, far vote 1, psi 79, advance 12
+FLOPS_FWD = 147      # soft forward step: chart 62, far vote 1, psi 72 (no floor), advance 12
 FLOPS_REPLAY = 213   # replay step: chart 62, vote 1, Phi 54, new point 4, advance 10,
                      # VJP 63, wave reduction 19
 # HBM bytes per k_fit_fused launch at the bench workload, from rocprofv3 --pmc

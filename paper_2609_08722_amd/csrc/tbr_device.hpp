@@ -51,7 +51,8 @@ struct __align__(16) StrokeRec {
   float per_r;      // Steiner perimeter P_l(r) = 2 l + 2 pi r
   float inv_wd;     // 1 / max(tau r, tau_min)
   float floor_c;    // (eps r)^2
-  float far_sig;    // r + 28 wd: beyond it the coverage is below sigmoid(-28)
+  float far_sig;    // r + 28 wd (at least): beyond it the coverage is below
+                    // sigmoid(-28) and psi's floor cannot bind
   float dwd_dr;     // d max(tau r, tau_min) / dr: tau or 0
   float cr, cg, cb; // colour c_i = softmax(z_i / tau_c) P (or P[argmax])
   int label;        // argmax_k z_ik (hard colour index)
@@ -272,15 +273,17 @@ struct Move {
 // kPer: also return 1 / P_l(sig_o). The root of Eq. (back) / Eq. (fwd)
 // satisfies sqrt(l^2 + pi q) = l + pi sig_o, so P_l(sig_o) =
 // 2 sqrt(l^2 + pi q): one reciprocal square root gives both.
-template <bool kPer = false>
+// kFloor = false: psi of a point where the floor cannot bind (C > (eps r)^2
+// known beforehand), without the floor's test and terms.
+template <bool kPer = false, bool kFloor = true>
 __device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, bool backward,
                                          const Leaf& lf) {
   Move m;
   const float two_ell = g.two_ell;
   // psi: Eq. (back) with the implemented floor; Phi: Eq. (fwd)
   float cq = back_area(c.sig, lf, two_ell);
-  m.floored = backward && cq < g.floor_c;
-  float q = backward ? fmaxf(cq, g.floor_c) : fwd_area(c.sig, lf, two_ell);
+  m.floored = kFloor && backward && cq < g.floor_c;
+  float q = backward ? (kFloor ? fmaxf(cq, g.floor_c) : cq) : fwd_area(c.sig, lf, two_ell);
   float num =
       backward ? (m.floored ? g.floor_c - c.sig * fmaf(kPi, c.sig, two_ell) : -lf.ar) : lf.ar;
   if constexpr (kPer) {

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "tbr_device.hpp"
 #include "tbr_kernels.hpp"
 
@@ -45,7 +47,13 @@ __device__ __forceinline__ StrokeRec prep_stroke(const KProgram& p, const KOpts&
   g.dwd_dr = rel ? o.tau : 0.f;
   float er = o.eps * r;
   g.floor_c = er * er;
-  g.far_sig = fmaf(-kFarZ, wd, r);
+  // beyond far_sig a wave skips coverage, and under uniform insertion psi's
+  // floor cannot bind there either: far_sig is at least the distance where
+  // A_l(s) - A_l(r) reaches (eps r)^2 (cancellation-free root, with a margin
+  // for the kernels' FP32 C)
+  const float a_fl = g.ar + g.floor_c;
+  const float s_fl = a_fl / (ell + sqrtf(fmaf(ell, ell, kPi * a_fl)));
+  g.far_sig = fmaxf(fmaf(-kFarZ, wd, r), s_fl * 1.001f);
   // colour: softmax(z / tau_c) P, or P[argmax z] when tau_c == 0
   const float* z = p.logits + (size_t)i * p.k;
   int best = 0;
@@ -175,48 +183,71 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
   // states x_k, x_2k, ... (< x_n) are checkpointed; x_{i+1} is the input of
   // stroke i, so the first one met going down is at i = floor((n-1)/k) k - 1
   int next_ck = k > 0 ? ((n - 1) / k) * k - 1 : -1;
-  for (int i = n - 1; i >= 0; --i) {
-    const StrokeRec g = load_rec(recs, i);
-    if (kTape && i == next_ck) {
-      if (write_tape) {
-        size_t o = (size_t)((i + 1) / k) * P + id.p;
-        tape.ckpt_xy[o] = make_double2(x, y);
-        tape.ckpt_t[o] = make_float2(tm, (float)te);
-      }
-      next_ck -= k;
-    }
-    Chart c = chart(x, y, g);
-    const Leaf lf = leaf_at<kT == kCoupled>(c, g, coup, i);
-    // Coverage and compositing, unless the stroke is far from every pixel
-    // of the wave: then alpha < 7e-13, 1 - alpha rounds to 1 and T and C
-    // are unchanged to FP32 rounding. Lanes past a ragged canvas edge trace
-    // a point just outside the canvas and vote too: that can only keep the
-    // exact path.
-    if (!wave_all(is_far<kT == kCoupled>(c.sig, lf, g))) {
-      Cover v = cover(c.sig, g, lf.r);
-      float t = trans_value(tm, te);
-      float ta = t * v.alpha;
-      cr = fmaf(ta, g.cr, cr);
-      cg = fmaf(ta, g.cg, cg);
-      cb = fmaf(ta, g.cb, cb);
-      tm *= v.q;
-      renorm(tm, te);
-    }
+  // Under uniform insertion a far point is never floored (far_sig), so the
+  // far steps run psi without the floor and record no side-table entry.
+  constexpr bool kFloorFar = kT != kCapsule;
+  // psi (or R_D's drops) and the advance of one step, with the floor and its
+  // record when kFloor
+  auto transport = [&](int i, const Chart& c, const StrokeRec& g, const Leaf& lf, auto floor_tag) {
+    constexpr bool kFloor = decltype(floor_tag)::value;
     if constexpr (kT == kDrops) {
       drops_backward(x, y, g);  // R_D: rendered only, no tape
     } else if constexpr (kT != kInert) {
-      // backward map with the implemented floor; record where it binds
-      Move mv = displace(c, g, true, lf);
-      if (mv.floored) {
-        if (write_tape && nrec < tape.side_slots) {
-          size_t o = (size_t)nrec * P + id.p;
-          tape.side_idx[o] = i;
-          tape.side_xy[o] = make_double2(x, y);
+      Move mv = displace<false, kFloor>(c, g, true, lf);
+      if constexpr (kFloor) {  // record where the floor binds
+        if (mv.floored) {
+          if (write_tape && nrec < tape.side_slots) {
+            size_t o = (size_t)nrec * P + id.p;
+            tape.side_idx[o] = i;
+            tape.side_xy[o] = make_double2(x, y);
+          }
+          ++nrec;
         }
-        ++nrec;
       }
       advance(x, y, c, mv, g);
     }
+  };
+  int i = n - 1;
+  while (i >= 0) {
+    // Strokes far from every pixel of the wave, up to the next one that is
+    // not: alpha < 7e-13, so 1 - alpha rounds to 1 and T and C are
+    // unchanged to FP32 rounding. Lanes past a ragged canvas edge trace a
+    // point just outside the canvas and vote too: that can only keep the
+    // exact path. The near stroke leaves the loop with its chart.
+    StrokeRec g;
+    Chart c;
+    Leaf lf;
+    bool near = false;
+    for (; i >= 0; --i) {
+      g = load_rec(recs, i);
+      if (kTape && i == next_ck) {
+        if (write_tape) {
+          size_t o = (size_t)((i + 1) / k) * P + id.p;
+          tape.ckpt_xy[o] = make_double2(x, y);
+          tape.ckpt_t[o] = make_float2(tm, (float)te);
+        }
+        next_ck -= k;
+      }
+      c = chart(x, y, g);
+      lf = leaf_at<kT == kCoupled>(c, g, coup, i);
+      if (!wave_all(is_far<kT == kCoupled>(c.sig, lf, g))) {
+        near = true;
+        break;
+      }
+      transport(i, c, g, lf, std::integral_constant<bool, kFloorFar>{});
+    }
+    if (!near) break;
+    // a near stroke: coverage and compositing, then psi with the floor
+    Cover v = cover(c.sig, g, lf.r);
+    float t = trans_value(tm, te);
+    float ta = t * v.alpha;
+    cr = fmaf(ta, g.cr, cr);
+    cg = fmaf(ta, g.cg, cg);
+    cb = fmaf(ta, g.cb, cb);
+    tm *= v.q;
+    renorm(tm, te);
+    transport(i, c, g, lf, std::integral_constant<bool, true>{});
+    --i;
   }
   float t = trans_value(tm, te);
   SoftOut o;
