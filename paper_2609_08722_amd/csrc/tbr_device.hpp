@@ -1,7 +1,7 @@
 // tbr_device.hpp -- per-lane FP32 arithmetic of the capsule transport.
 //
 // One pixel per lane. Stroke constants arrive as a wave-uniform 80-byte
-// record (scalar loads); everything else lives in VGPRs. All maps are the
+// record; everything else lives in VGPRs. All maps are the
 // closed forms of Sec. 4 of the paper (TBR, arxiv 2609.08722):
 //   distance sigma to the segment, Steiner area A_l(s) = 2 l s + pi s^2 and
 //   perimeter P_l(s) = 2 l + 2 pi s (Eq. steiner), the centred arclength

@@ -3,8 +3,10 @@
 // Pixel layout: a block of 256 threads is 4 waves; each wave owns an 8x8
 // pixel tile (lane l -> (l & 7, l >> 3)), the block a 16x16 tile. Pixel
 // centres are ((j + .5) / W, (i + .5) / H), row-major. Stroke records are
-// read with wave-uniform addresses (scalar loads into SGPRs); no stroke data
-// is staged through LDS in the trace kernels.
+// read with wave-uniform addresses: scalar loads into SGPRs in the trace
+// kernels, vector loads where a loop holds a barrier (the replay, the fused
+// and serving kernels). No stroke data is staged through LDS: it measured
+// no faster (see load_rec).
 //
 // Paper references (TBR, arxiv 2609.08722): Eq. chain and Eq. render
 // (Sec. 3), the operator (Sec. 4), Eq. relax (Sec. 5.1), Eq. state, the
@@ -113,9 +115,13 @@ __global__ void __launch_bounds__(256) k_serve_prep(const ServePrep* __restrict_
   if (b >= q.block0 && i < q.prog.n) q.out[i] = prep_stroke(q.prog, q.opts, i);
 }
 
-
-// Wave-uniform load of a stroke record (the index is uniform, so the
-// compiler issues scalar loads).
+// Wave-uniform load of a stroke record. The compiler issues scalar loads
+// where it can prove that no store of the launch changes the record (the
+// trace kernels' barrier-free loops) and vector loads otherwise. Forcing
+// either kind measured slower: scalar loads in the replay and fused kernels
+// (at their occupancy the scalar cache's latency shows), the records staged
+// through LDS per chunk, and vector loads in the trace kernels (more VGPRs,
+// fewer waves).
 __device__ __forceinline__ StrokeRec load_rec(const StrokeRec* __restrict__ recs, int i) {
   i = __builtin_amdgcn_readfirstlane(i);
   return recs[i];
