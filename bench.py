@@ -46,7 +46,7 @@ FLOPS_REPLAY = 213   # replay step: chart 62, vote 1, Phi 54, new point 4, advan
 # HBM bytes per k_fit_fused launch at the bench workload, from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
 # in the same runs; valid only for the kernel sources it was measured on.
-TRAFFIC = {"sha": "5c7ace77e1178780", "bytes": 348.3e6 + 572.7e6}
+TRAFFIC = {"sha": "96b046893888a7ec", "bytes": 348.3e6 + 572.7e6}
 
 
 def kernel_sha():
