@@ -49,13 +49,11 @@ __device__ __forceinline__ StrokeRec prep_stroke(const KProgram& p, const KOpts&
   g.dwd_dr = rel ? o.tau : 0.f;
   float er = o.eps * r;
   g.floor_c = er * er;
-  // beyond far_sig a wave skips coverage, and under uniform insertion psi's
-  // floor cannot bind there either: far_sig is at least the distance where
-  // A_l(s) - A_l(r) reaches (eps r)^2 (cancellation-free root, with a margin
-  // for the kernels' FP32 C)
-  const float a_fl = g.ar + g.floor_c;
-  const float s_fl = a_fl / (ell + sqrtf(fmaf(ell, ell, kPi * a_fl)));
-  g.far_sig = fmaxf(fmaf(-kFarZ, wd, r), s_fl * 1.001f);
+  // beyond far_sig a wave skips coverage, and psi's floor cannot bind there
+  // on any leaf: C = (sigma - rl)(pi (sigma + rl) + 2 l) >= pi (sigma - rl)^2
+  // exceeds (eps r)^2 once sigma - rl > eps r / sqrt(pi) (with a margin for
+  // the kernels' FP32 C); at the usual eps that is far inside 28 wd
+  g.far_sig = r + fmaxf(-kFarZ * wd, er * (1.001f / sqrtf(kPi)));
   // colour: softmax(z / tau_c) P, or P[argmax z] when tau_c == 0
   const float* z = p.logits + (size_t)i * p.k;
   int best = 0;
@@ -189,9 +187,8 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
   // states x_k, x_2k, ... (< x_n) are checkpointed; x_{i+1} is the input of
   // stroke i, so the first one met going down is at i = floor((n-1)/k) k - 1
   int next_ck = k > 0 ? ((n - 1) / k) * k - 1 : -1;
-  // Under uniform insertion a far point is never floored (far_sig), so the
-  // far steps run psi without the floor and record no side-table entry.
-  constexpr bool kFloorFar = kT != kCapsule;
+  // A far point is never floored (far_sig), so the far steps run psi
+  // without the floor and record no side-table entry.
   // psi (or R_D's drops) and the advance of one step, with the floor and its
   // record when kFloor
   auto transport = [&](int i, const Chart& c, const StrokeRec& g, const Leaf& lf, auto floor_tag) {
@@ -240,7 +237,7 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
         near = true;
         break;
       }
-      transport(i, c, g, lf, std::integral_constant<bool, kFloorFar>{});
+      transport(i, c, g, lf, std::integral_constant<bool, false>{});
     }
     if (!near) break;
     // a near stroke: coverage and compositing, then psi with the floor
