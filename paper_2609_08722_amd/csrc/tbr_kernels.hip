@@ -284,6 +284,14 @@ __device__ __forceinline__ void hard_pixel(const StrokeRec* __restrict__ recs,
     if (!done) {
       Chart c = chart(x, y, g);
       const Leaf lf = leaf_at<kT == kCoupled>(c, g, coup, i);
+      if constexpr (kT == kCapsule || kT == kCoupled) {
+        // Every lane still tracing lies beyond the stroke's far margin: none
+        // can hit it, and psi's floor cannot bind there.
+        if (wave_all(is_far<kT == kCoupled>(c.sig, lf, g))) {
+          advance(x, y, c, displace<false, false>(c, g, true, lf), g);
+          continue;
+        }
+      }
       if (c.sig <= lf.r) {  // closed footprint
         done = true;
         own = i;
