@@ -117,10 +117,12 @@ struct Chart {
 __device__ __forceinline__ Chart chart(double x, double y, const StrokeRec& g) {
   Chart c;
   float dx = (float)(x - g.mx), dy = (float)(y - g.my);
-  c.s = fmaf(dx, g.ce, dy * g.se);
-  c.h = fmaf(dy, g.ce, -(dx * g.se));
-  c.sgs = c.s < 0.f ? -1.f : 1.f;
-  c.sgh = c.h < 0.f ? -1.f : 1.f;
+  // The inner products take + 0, so s and h are never -0 and each fold sign,
+  // one bit insert, is sgn with sgn(0) = +1.
+  c.s = fmaf(dx, g.ce, fmaf(dy, g.se, 0.f));
+  c.h = fmaf(dy, g.ce, fmaf(-dx, g.se, 0.f));
+  c.sgs = copysignf(1.f, c.s);
+  c.sgh = copysignf(1.f, c.h);
   c.S = fabsf(c.s);
   c.H = fabsf(c.h);
   c.E = fmaxf(c.S - g.hl, 0.f);
