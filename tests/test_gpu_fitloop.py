@@ -136,7 +136,7 @@ def test_loop_fits_and_stays_in_windows():
     losses = [fit.step_checked(target).item() for _ in range(50)]
     after = hard_mse()
     # the soft losses along the schedule are taken at different tau, so the
-    # fit is judged on the hard render, which the annealing ends at
+    # fit is evaluated on the hard render, which the annealing ends at
     log(f"[loop] loss {losses[0]:.5f} -> {losses[-1]:.5f}; hard MSE {before:.5f} -> {after:.5f}")
     assert np.all(np.isfinite(losses))
     assert after < 0.75 * before
