@@ -270,7 +270,22 @@ struct Move {
   float th_o, sn_o, cs_o;  // cap angle of the new point and its sin / cos
   float inv_per_o;       // 1 / P_l(sig_o) (kPer only)
   bool floored;          // psi only: the floor C >= (eps r)^2 bound
+  // Increments new - old of the chart coordinates, each formed without
+  // cancellation (the replay's adjoint is built on them; unused elsewhere):
+  float dsig, dth, dsin, dcos;
+  float tf, tf_o;        // flank part min(S, l/2) of the arclength, old and new point
+  float dtf;             // tf_o - tf
+  bool all_cap;          // regenerate only: every lane of the wave on the cap
 };
+
+// Flank part of the arclength of both points and its increment: dS itself
+// when both lie on the flank, 0 when both lie on a cap.
+__device__ __forceinline__ void flank_part(const Chart& c, const StrokeRec& g, Move& m) {
+  const float S_o = c.S + m.dS;
+  m.tf = fminf(c.S, g.hl);
+  m.tf_o = fminf(S_o, g.hl);
+  m.dtf = fmaxf(c.S, S_o) <= g.hl ? m.dS : m.tf_o - m.tf;
+}
 
 // kPer: also return 1 / P_l(sig_o). The root of Eq. (back) / Eq. (fwd)
 // satisfies sqrt(l^2 + pi q) = l + pi sig_o, so P_l(sig_o) =
@@ -320,6 +335,11 @@ __device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, boo
   float extra = (cap_in && cap_out) ? 0.f : dt - dsig * th_o - c.sig * dth;
   m.dS = fmaf(dsig, m.sn_o, fmaf(c.sig, dsin, extra));
   m.dH = fmaf(dsig, m.cs_o, c.sig * dcos);
+  m.dsig = dsig;
+  m.dth = dth;
+  m.dsin = dsin;
+  m.dcos = dcos;
+  flank_part(c, g, m);
   return m;
 }
 
@@ -342,7 +362,8 @@ __device__ __forceinline__ Move regenerate(const Chart& c, const StrokeRec& g, c
   const bool cap_in = c.th > 0.f;
   const float dth_cc = dsig * g.ell * (kPi - 2.f * c.th) * (c.inv_per * inv_sig_o);
   float dth, th_o, extra;
-  if (wave_all(cap_in)) {
+  const bool all_cap = wave_all(cap_in);
+  if (all_cap) {
     dth = dth_cc;
     th_o = c.th + dth;
     extra = 0.f;
@@ -368,6 +389,18 @@ __device__ __forceinline__ Move regenerate(const Chart& c, const StrokeRec& g, c
   m.th_o = th_o;
   m.dS = fmaf(dsig, m.sn_o, fmaf(c.sig, dsin, extra));
   m.dH = fmaf(dsig, m.cs_o, c.sig * dcos);
+  m.dsig = dsig;
+  m.dth = dth;
+  m.dsin = dsin;
+  m.dcos = dcos;
+  m.all_cap = all_cap;
+  if (all_cap) {  // both points on the cap: the flank part is l/2 throughout
+    m.tf = g.hl;
+    m.tf_o = g.hl;
+    m.dtf = 0.f;
+  } else {
+    flank_part(c, g, m);
+  }
   return m;
 }
 
@@ -452,26 +485,48 @@ __device__ __forceinline__ float trans_value(float tm, int te) {
 }
 
 // Vector-Jacobian product of one stroke step (Eq. adjstep, Eq. adjparam):
-// given gx, gy = lambda^x_{i-1} (adjoint of the map's output psi_i(x_i))
-// and mu = adjoint of alpha_i, return lambda^x_i and the stroke's
-// contributions d/d(m_x, m_y, phi, l, r). The map is differentiated in
-// reverse through: local frame, distance, fraction, area root, and the
-// reconstruction at the new distance; coverage enters through sigma'.
+// given lx, ly = lambda^x_{i-1} (the adjoint of the map's output
+// psi_i(x_i)) and mu = the adjoint of alpha_i, return lambda^x_i and the
+// stroke's contributions d/d(m_x, m_y, phi, l, r).
 //
-// Inputs describe the map at its input point x_i ("in") and output point
-// x_{i-1} ("out"), as produced by either direction of the map.
+// In the chart of Sec. 4 the map takes (sigma', w) to (rho, w) on the same
+// leaf, and the output is the reconstruction at (rho, w). The adjoint of the
+// output point is carried by two numbers: the adjoint of rho with w fixed
+// (which gives Cb, the adjoint of the area C, through rho = A_l^{-1}(C)) and
+// the adjoint t'b of its arclength t' = w P_l(rho); in the folded frame the
+// output's adjoint is A_o (sin th', cos th') + t'b (cos th', -sin th').
+//
+// Far from a stroke the map is close to the identity, and three results are
+// small differences of terms of the size of the distance: lambda^x_i -
+// lambda^x_{i-1} (minus the centre's contribution), the half-length's
+// adjoint, and the angle's. The construction is invariant under rotations
+// about m, so d psi / d phi = J (psi(x) - m) - D psi J (x - m) with J the
+// quarter turn: two lever arms. Each of the three is therefore written in
+// the increments output - input of the chart coordinates (dsig, dth, dsin,
+// dcos, dtf), which the map forms without cancellation. For the angle the
+// quarter turn is the chart velocity (a, b) per unit angle of the folded
+// first-quadrant point, times sgs sgh:
+//   a = tf cos th,  b = (tf (th cos th - sin th) - sigma - 2 pi w tf cos th)
+//                       / P_l(sigma),
+// tf = min(S, l/2), so that, with P0 = P_l(rho), P1 = P_l(sigma'),
+//   lambda . d psi / d phi = sgs sgh [Cb (P0 a_o - P1 a_i) + t'b P0 (b_o - b_i)
+//                                     + (coverage and coupling terms)],
+// and P0 a_o - P1 a_i and P0 (b_o - b_i) expand into the increments.
 struct VjpIn {
+  float sgs, sgh;        // signs of the signed local coordinates (kept by the map)
+  float w;               // centred arclength fraction (common to both points)
   // input point x_i
-  float s, h, sgs, sgh;  // signed local coordinates and signs
   float sig;             // sigma' = distance of x_i
   float th, sn, cs;      // cap angle of x_i and its sin / cos (0, 0, 1 on the flank)
-  float w;               // centred arclength fraction (common to both points)
+  float tf;              // flank part min(S, l/2) of x_i's arclength
   float inv_p1;          // 1 / P_l(sigma') (0 at a drop centre)
   // output point x_{i-1}
-  float so, ho;          // signed local coordinates
   float rho;             // distance of x_{i-1}
-  float inv_rho, inv_p0; // 1 / rho and 1 / P_l(rho)
+  float inv_p0;          // 1 / P_l(rho)
   float th_o, sn_o, cs_o;
+  float tf_o;
+  // increments x_{i-1} - x_i of the chart coordinates
+  float dsig, dth, dsin, dcos, dtf;
   bool floored;          // the floor C >= (eps r)^2 bound at x_i
   // coverage at x_i
   float z, alpha, q;
@@ -502,7 +557,8 @@ __device__ __forceinline__ VjpOut vjp_cover_only(const Chart& c, const StrokeRec
   o.gy = 0.f;
   o.gmx = -gx;
   o.gmy = -gy;
-  o.gphi = fmaf(ssb, c.h, -(shb * c.s));
+  // turning the stroke by dphi changes sigma as turning the point by -dphi
+  o.gphi = zw * (c.sgs * c.sgh) * (fminf(c.S, g.hl) * c.cs);
   o.gell = -0.5f * eb;
   return o;
 }
@@ -516,128 +572,128 @@ __device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, f
                                            float ly, float mu, const Leaf& lf) {
   VjpOut o;
   const float two_ell = g.two_ell;
-  // out = m + sgs S' e + sgh H' n
-  float ge = fmaf(lx, g.ce, ly * g.se);
-  float gn = fmaf(ly, g.ce, -(lx * g.se));
-  float sbp = v.sgs * ge;  // adjoint of S'
-  float hbp = v.sgh * gn;  // adjoint of H'
-  o.gmx = lx;
-  o.gmy = ly;
-  o.gphi = fmaf(v.so, gn, -(v.ho * ge));
-  // S' = min(t', l/2) + rho sin th', H' = rho cos th', th' = (t' - l/2) / rho
-  // th' has adjoint rho (S'b cos th' - H'b sin th'), and t' has it over
-  // rho. A far stroke's output point is at rho > r + 28 wd > 0, where the
-  // factors rho and 1 / rho cancel; elsewhere rho may be 0 (a point on the
-  // segment), where th' is held at 0 and passes nothing on.
-  float tpb;
+  // output point m + sgs S' e + sgh H' n
+  const float ge = fmaf(lx, g.ce, ly * g.se);
+  const float gn = fmaf(ly, g.ce, -(lx * g.se));
+  const float sbp = v.sgs * ge, hbp = v.sgh * gn;
+  const float tpb = fmaf(sbp, v.cs_o, -(hbp * v.sn_o));  // adjoint of t'
+  const float ao = fmaf(sbp, v.sn_o, hbp * v.cs_o);
+  const float tw = kTwoPi * v.w;
+  // rho's adjoint with w fixed (through S', H' and t' = w P_l(rho)), then
+  // C's: rho = A_l^{-1}(C), dC = P_l(rho) drho + 2 rho dl
+  const float cb = fmaf(tpb, tw - v.th_o, ao) * v.inv_p0;
+  const float p0 = fmaf(kTwoPi, v.rho, two_ell);
+  const float p1 = fmaf(kTwoPi, v.sig, two_ell);
+  const float t1 = kTwoPi * v.dsig;  // P0 - P1
+  const float du = v.dsig * v.inv_p1;
+  const float u = kTwoPi * du;       // (P0 - P1) / P1
+  float zw = 0.f;
   if constexpr (kCover) {
-    const float thb = v.rho * fmaf(sbp, v.cs_o, -(hbp * v.sn_o));
-    tpb = thb * v.inv_rho;
-  } else {
-    tpb = fmaf(sbp, v.cs_o, -(hbp * v.sn_o));
+    const float zb = v.clamped ? 0.f : mu * v.alpha * v.q;
+    zw = zb * g.inv_wd;  // minus sigma''s adjoint from z = (edge - sigma') / wd
   }
-  float rhob = fmaf(sbp, v.sn_o, hbp * v.cs_o) - tpb * v.th_o;
-  float hlb = sbp - tpb;
-  // t' = w P_l(rho)
-  float p0 = fmaf(kTwoPi, v.rho, two_ell);
-  float wb = tpb * p0;
-  rhob = fmaf(kTwoPi * v.w, tpb, rhob);
-  float ellb = 2.f * v.w * tpb;
-  // rho = A_l^{-1}(C): dC = P_l(rho) drho + 2 rho dl
-  float cb = rhob * v.inv_p0;
-  ellb = fmaf(-2.f * v.rho, cb, ellb);
-  // C = A_l(sigma') - A_l(r), or the floor (eps r)^2
-  float p1 = fmaf(kTwoPi, v.sig, two_ell);
   const float pr = g.per_r;
-  float sigb = v.floored ? 0.f : cb * p1;
+  float wbx = 0.f, ellx = 0.f, rl_c;
+  // C = A_l(sigma') - A_l(r) (coupled: - G), or the floor (eps r)^2
   if constexpr (kCoupled) {
-    // C = A_l(sigma') - G
     o.gr = v.floored ? cb * dfloor_dr(g) : -(cb * pr * lf.g);
-    ellb = v.floored ? ellb : fmaf(2.f * fmaf(-g.r, lf.g, v.sig), cb, ellb);
-    wb = v.floored ? wb : fmaf(-cb * g.ar, lf.dg, wb);
-    // coverage z = (rl - sigma') / wd, before w's adjoint is passed on
+    wbx = v.floored ? 0.f : -cb * g.ar * lf.dg;
+    rl_c = v.floored ? -v.rho : fmaf(-g.r, lf.g, -v.dsig);
     if constexpr (kCover) {
-      float zb = v.clamped ? 0.f : mu * v.alpha * v.q;
-      float zw = zb * g.inv_wd;
-      sigb -= zw;
-      float rlb = zw * lf.inv_per;  // adjoint of G through rl
+      // coverage z = (rl - sigma') / wd: rl follows G
+      const float rlb = zw * lf.inv_per;
       o.gr = fmaf(rlb * pr, lf.g, fmaf(-zw * v.z, g.dwd_dr, o.gr));
-      ellb = fmaf(2.f * rlb, fmaf(g.r, lf.g, -lf.r), ellb);
-      wb = fmaf(rlb * g.ar, lf.dg, wb);
+      ellx = 2.f * rlb * fmaf(g.r, lf.g, -lf.r);
+      wbx = fmaf(rlb * g.ar, lf.dg, wbx);
     }
   } else {
     o.gr = v.floored ? cb * dfloor_dr(g) : -(cb * pr);
-    ellb = v.floored ? ellb : fmaf(2.f * (v.sig - g.r), cb, ellb);
+    rl_c = v.floored ? -v.rho : -v.dsig - g.r;
+    if constexpr (kCover) o.gr = fmaf(zw, fmaf(-v.z, g.dwd_dr, 1.f), o.gr);
   }
-  // w = t / P_l(sigma')
-  float tb = wb * v.inv_p1;
-  sigb = fmaf(-kTwoPi * v.w, tb, sigb);
-  ellb = fmaf(-2.f * v.w, tb, ellb);
-  // t = min(S, l/2) + sigma' th, th = atan2(E, H), E = S - l/2 (cap form,
-  // exact on the flank too since th = 0 there)
-  hlb += tb;
-  sigb = fmaf(v.th, tb, sigb);
-  float eb = tb * v.cs;
-  float hb = -(tb * v.sn);
-  // coverage: z = (r - sigma') / wd
-  if constexpr (kCover && !kCoupled) {
-    float zb = v.clamped ? 0.f : mu * v.alpha * v.q;
-    float zw = zb * g.inv_wd;
-    sigb -= zw;
-    o.gr = fmaf(zw, fmaf(-v.z, g.dwd_dr, 1.f), o.gr);
+  // t's adjoint at the input, (t'b P0 + wbx) / P1, in excess of t'b
+  const float dT = kCoupled ? fmaf(wbx, v.inv_p1, tpb * u) : tpb * u;
+  const float kap = v.th - tw;
+  // sigma''s adjoint at the input (C through P1, w = t / P1, t's cap term,
+  // the coverage), in excess of A_o
+  const float dsg = fmaf(kap, dT, -fmaf(v.dth, tpb, cb * (v.floored ? p0 : t1))) - zw;
+  // lambda^x_i - lambda^x_{i-1} in the folded frame
+  const float de = fmaf(dsg, v.sn, fmaf(dT, v.cs, -fmaf(ao, v.dsin, tpb * v.dcos)));
+  const float dh = fmaf(dsg, v.cs, fmaf(-dT, v.sn, fmaf(-ao, v.dcos, tpb * v.dsin)));
+  // l: through t' and w, the area root, C, and l/2 in the chart and the
+  // reconstruction (adjoint dT - de)
+  o.gell = fmaf(0.5f, dT - de, fmaf(-2.f * v.w, dT, fmaf(2.f * cb, rl_c, ellx)));
+  // phi: Cb (P0 a_o - P1 a_i) + t'b P0 (b_o - b_i) + zw a_i - wbx b_i
+  const float Y = v.floored ? p0 * v.tf_o * v.cs_o
+                            : fmaf(t1 * v.tf_o, v.cs_o, p1 * fmaf(v.dtf, v.cs_o, v.tf * v.dcos));
+  float br = fmaf(v.dth, v.cs_o, -v.dsin);
+  br = fmaf(kap, v.dcos, br);
+  br = fmaf(-u, fmaf(kap, v.cs, -v.sn), br);
+  float X = fmaf(v.tf, br, -two_ell * du);
+  X = fmaf(v.dtf, fmaf(v.th_o - tw, v.cs_o, -v.sn_o), X);
+  float ang = fmaf(cb, Y, fmaf(tpb, X, zw * v.tf * v.cs));
+  if constexpr (kCoupled) {
+    ang = fmaf(-wbx * v.inv_p1, fmaf(v.tf, fmaf(kap, v.cs, -v.sn), -v.sig), ang);
   }
-  // sigma' = sqrt(H^2 + E^2)
-  hb = fmaf(sigb, v.cs, hb);
-  eb = fmaf(sigb, v.sn, eb);
-  // E = S - l/2
-  float sb = eb;
-  hlb -= eb;
-  // S = |s|, H = |h|; s = d.e, h = d.n, d = x - m
-  float ssb = v.sgs * sb, shb = v.sgh * hb;
-  o.gx = fmaf(ssb, g.ce, -(shb * g.se));
-  o.gy = fmaf(ssb, g.se, shb * g.ce);
-  o.gmx -= o.gx;
-  o.gmy -= o.gy;
-  o.gphi = fmaf(ssb, v.h, fmaf(-shb, v.s, o.gphi));
-  o.gell = fmaf(0.5f, hlb, ellb);
+  o.gphi = (v.sgs * v.sgh) * ang;
+  // unfold the adjoint increment
+  const float ssd = v.sgs * de, shd = v.sgh * dh;
+  const float dx = fmaf(ssd, g.ce, -(shd * g.se));
+  const float dy = fmaf(ssd, g.se, shd * g.ce);
+  o.gx = lx + dx;
+  o.gy = ly + dy;
+  o.gmx = -dx;
+  o.gmy = -dy;
   return o;
 }
 
 // vjp_step<false> for the replay's common step under uniform insertion: the
-// stroke is far from the wave (no coverage terms), no lane is floored, and
-// the input point x_i is the regenerated one, at sigma' > rho > 0. The same
-// adjoint with its terms gathered: the rho and 1 / rho of th' cancel, the
-// th' and 2 pi w terms of rho's and sigma''s adjoints share one factor each,
-// and the four terms of l's adjoint collapse to
-// 2 (w (t'b - tb) + (sigma' - rho - r) Cb).
+// stroke is far from the wave (no coverage terms) and no lane is floored.
+// kCapCap: every lane of the wave lies on the cap at both points (tf = l/2,
+// dtf = 0), the case of almost every wave a stroke is far from.
+template <bool kCapCap>
 __device__ __forceinline__ VjpOut vjp_far(const VjpIn& v, const StrokeRec& g, float lx, float ly) {
   VjpOut o;
-  const float two_ell = g.two_ell;
   const float ge = fmaf(lx, g.ce, ly * g.se);
   const float gn = fmaf(ly, g.ce, -(lx * g.se));
-  const float sbp = v.sgs * ge;  // adjoint of S'
-  const float hbp = v.sgh * gn;  // adjoint of H'
-  const float gphi0 = fmaf(v.so, gn, -(v.ho * ge));
-  const float tpb = fmaf(sbp, v.cs_o, -(hbp * v.sn_o));  // adjoint of t'
+  const float sbp = v.sgs * ge, hbp = v.sgh * gn;
+  const float tpb = fmaf(sbp, v.cs_o, -(hbp * v.sn_o));
+  const float ao = fmaf(sbp, v.sn_o, hbp * v.cs_o);
   const float tw = kTwoPi * v.w;
-  // rho: S' and H' directly, th' = (t' - l/2) / rho, and t' = w P_l(rho)
-  const float rhob = fmaf(tpb, tw - v.th_o, fmaf(sbp, v.sn_o, hbp * v.cs_o));
-  const float cb = rhob * v.inv_p0;  // rho = A_l^{-1}(C)
-  // w = t / P_l(sigma') receives t' P_l(rho); t passes it on
-  const float tb = tpb * (fmaf(kTwoPi, v.rho, two_ell) * v.inv_p1);
-  const float sigb = fmaf(v.th - tw, tb, cb * fmaf(kTwoPi, v.sig, two_ell));
+  const float cb = fmaf(tpb, tw - v.th_o, ao) * v.inv_p0;
+  const float p1 = fmaf(kTwoPi, v.sig, g.two_ell);
+  const float t1 = kTwoPi * v.dsig;
+  const float du = v.dsig * v.inv_p1;
+  const float u = kTwoPi * du;
+  const float dT = tpb * u;
   o.gr = -(cb * g.per_r);
-  const float ellh = fmaf(v.w, tpb - tb, ((v.sig - v.rho) - g.r) * cb);
-  const float eb = fmaf(sigb, v.sn, tb * v.cs);
-  const float hb = fmaf(sigb, v.cs, -(tb * v.sn));
-  const float hlb = (sbp - tpb + tb) - eb;
-  const float ssb = v.sgs * eb, shb = v.sgh * hb;
-  o.gx = fmaf(ssb, g.ce, -(shb * g.se));
-  o.gy = fmaf(ssb, g.se, shb * g.ce);
-  o.gmx = lx - o.gx;
-  o.gmy = ly - o.gy;
-  o.gphi = fmaf(ssb, v.h, fmaf(-shb, v.s, gphi0));
-  o.gell = fmaf(2.f, ellh, 0.5f * hlb);
+  const float kap = v.th - tw;
+  const float dsg = fmaf(kap, dT, -fmaf(v.dth, tpb, cb * t1));
+  const float de = fmaf(dsg, v.sn, fmaf(dT, v.cs, -fmaf(ao, v.dsin, tpb * v.dcos)));
+  const float dh = fmaf(dsg, v.cs, fmaf(-dT, v.sn, fmaf(-ao, v.dcos, tpb * v.dsin)));
+  o.gell = fmaf(0.5f, dT - de, fmaf(-2.f * v.w, dT, 2.f * cb * (-v.dsig - g.r)));
+  float br = fmaf(v.dth, v.cs_o, -v.dsin);
+  br = fmaf(kap, v.dcos, br);
+  br = fmaf(-u, fmaf(kap, v.cs, -v.sn), br);
+  float ang;
+  if constexpr (kCapCap) {
+    const float Y = fmaf(t1, v.cs_o, p1 * v.dcos);
+    const float X = fmaf(g.hl, br, -g.two_ell * du);
+    ang = fmaf(cb * g.hl, Y, tpb * X);
+  } else {
+    const float Y = fmaf(t1 * v.tf_o, v.cs_o, p1 * fmaf(v.dtf, v.cs_o, v.tf * v.dcos));
+    float X = fmaf(v.tf, br, -g.two_ell * du);
+    X = fmaf(v.dtf, fmaf(v.th_o - tw, v.cs_o, -v.sn_o), X);
+    ang = fmaf(cb, Y, tpb * X);
+  }
+  o.gphi = (v.sgs * v.sgh) * ang;
+  const float ssd = v.sgs * de, shd = v.sgh * dh;
+  const float dx = fmaf(ssd, g.ce, -(shd * g.se));
+  const float dy = fmaf(ssd, g.se, shd * g.ce);
+  o.gx = lx + dx;
+  o.gy = ly + dy;
+  o.gmx = -dx;
+  o.gmy = -dy;
   return o;
 }
 

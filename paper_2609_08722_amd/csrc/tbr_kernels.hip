@@ -634,29 +634,31 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
         const Leaf lf = leaf_at<kC>(ca, g, coup, i);
         if (!wave_all(is_far<kC>(ca.sig, lf, g))) break;
         Move mv = regenerate(ca, g, lf);
-        // unfolded displacement; the new point's signed coordinates are the
-        // chart's plus it (sgs (S + dS) = s + sgs dS, exactly)
+        // unfolded displacement; psi runs from the regenerated x_i back to
+        // the chart point x_{i-1}, so its increments are Phi's negated
         const float da = ca.sgs * mv.dS, db = ca.sgh * mv.dH;
         VjpIn vi;
         vi.sgs = ca.sgs;
         vi.sgh = ca.sgh;
         vi.w = ca.w;
         vi.floored = false;
-        vi.s = ca.s + da;
-        vi.h = ca.h + db;
         vi.sig = mv.sig_o;
         vi.th = mv.th_o;
         vi.sn = mv.sn_o;
         vi.cs = mv.cs_o;
+        vi.tf = mv.tf_o;
         vi.inv_p1 = mv.inv_per_o;
-        vi.so = ca.s;
-        vi.ho = ca.h;
         vi.rho = ca.sig;
-        vi.inv_rho = ca.inv_sig;
         vi.inv_p0 = ca.inv_per;
         vi.th_o = ca.th;
         vi.sn_o = ca.sn;
         vi.cs_o = ca.cs;
+        vi.tf_o = mv.tf;
+        vi.dsig = -mv.dsig;
+        vi.dth = -mv.dth;
+        vi.dsin = -mv.dsin;
+        vi.dcos = -mv.dcos;
+        vi.dtf = -mv.dtf;
         vi.z = 0.f;
         vi.alpha = 0.f;
         vi.q = 1.f;
@@ -665,8 +667,10 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
         VjpOut vo;
         if constexpr (kC) {
           vo = vjp_step<false, true>(vi, g, lx, ly, 0.f, lf);
+        } else if (mv.all_cap) {
+          vo = vjp_far<true>(vi, g, lx, ly);
         } else {
-          vo = vjp_far(vi, g, lx, ly);
+          vo = vjp_far<false>(vi, g, lx, ly);
         }
         lx = vo.gx;
         ly = vo.gy;
@@ -707,44 +711,45 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
         const Leaf lf = leaf_at<kC>(ca, g, coup, i);
         Move mv = displace<true>(ca, g, loaded, lf);
         const float da = ca.sgs * mv.dS, db = ca.sgh * mv.dH;
-        const float sn_pt = ca.s + da, hn_pt = ca.h + db;  // signed coordinates of the new point
         VjpIn vi;
         vi.sgs = ca.sgs;
         vi.sgh = ca.sgh;
         vi.w = ca.w;
         vi.floored = mv.floored;
+        // psi's increments x_{i-1} - x_i: the map's own for a loaded lane,
+        // Phi's negated for a regenerated one
+        const float sd = loaded ? 1.f : -1.f;
+        vi.dsig = sd * mv.dsig;
+        vi.dth = sd * mv.dth;
+        vi.dsin = sd * mv.dsin;
+        vi.dcos = sd * mv.dcos;
+        vi.dtf = sd * mv.dtf;
         if (loaded) {  // in = chart point x_i, out = psi_i(x_i)
-          vi.s = ca.s;
-          vi.h = ca.h;
           vi.sig = ca.sig;
           vi.th = ca.th;
           vi.sn = ca.sn;
           vi.cs = ca.cs;
-          vi.inv_p1 = ca.per > 0.f ? rcp(ca.per) : 0.f;
-          vi.so = sn_pt;
-          vi.ho = hn_pt;
+          vi.tf = mv.tf;
+          vi.inv_p1 = ca.per > 0.f ? ca.inv_per : 0.f;
           vi.rho = mv.sig_o;
-          vi.inv_rho = rcp(mv.sig_o);
-          vi.inv_p0 = rcp(fmaf(kTwoPi, mv.sig_o, g.two_ell));
+          vi.inv_p0 = mv.inv_per_o;
           vi.th_o = mv.th_o;
           vi.sn_o = mv.sn_o;
           vi.cs_o = mv.cs_o;
+          vi.tf_o = mv.tf_o;
         } else {  // in = regenerated x_i, out = chart point x_{i-1}
-          vi.s = sn_pt;
-          vi.h = hn_pt;
           vi.sig = mv.sig_o;
           vi.th = mv.th_o;
           vi.sn = mv.sn_o;
           vi.cs = mv.cs_o;
+          vi.tf = mv.tf_o;
           vi.inv_p1 = mv.inv_per_o;
-          vi.so = ca.s;
-          vi.ho = ca.h;
           vi.rho = ca.sig;
-          vi.inv_rho = ca.inv_sig;
           vi.inv_p0 = ca.inv_per;
           vi.th_o = ca.th;
           vi.sn_o = ca.sn;
           vi.cs_o = ca.cs;
+          vi.tf_o = mv.tf;
           step_by(x, y, da, db, g);
         }
         Cover cv = cover(vi.sig, g, lf.r);

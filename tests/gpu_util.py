@@ -16,14 +16,24 @@ def log(*a):
     print(*a, flush=True)
 
 
+# Exempt pixels are a geometric band (trajectories passing within 1e-5 of a
+# footprint edge): the oracle's own fraction is 0.02-0.34% on the parity
+# workloads (0.12% at 1024^2 x 2000), so more than 0.5% (+2 pixels on tiny
+# canvases) means the exemption itself is wrong.
+MAX_EXEMPT_FRAC = 0.005
+
+
 def hard_parity(gpu_owner, gpu_label, ref, tol=1e-5):
     """Owners and labels must agree except where the oracle's FP64 trajectory
-    passed within tol of a footprint boundary. Returns (exempt, mismatches)."""
+    passed within tol of a footprint boundary, and the exempt set must stay a
+    thin band. Returns (exempt, mismatches)."""
     go = np.asarray(gpu_owner).reshape(-1)
     gl = np.asarray(gpu_label).reshape(-1)
     exempt = ref["dmin"] < tol
     bad = ((go != ref["owner"]) | (gl != ref["label"])) & ~exempt
-    return int(exempt.sum()), int(bad.sum())
+    n_ex = int(exempt.sum())
+    assert n_ex <= MAX_EXEMPT_FRAC * exempt.size + 2, (n_ex, exempt.size)
+    return n_ex, int(bad.sum())
 
 
 def group_errors(gpu: np.ndarray, ref: np.ndarray):
@@ -43,3 +53,19 @@ def componentwise_ok(gpu, ref, rtol):
     lim = rtol * (np.abs(r) + 0.01 * rms) + 1e-30
     ratio = np.abs(g - r) / lim
     return float(np.mean(ratio > 1)), float(ratio.max() if ratio.size else 0.0)
+
+
+def assert_grads(gpu: dict, ref: dict, rtol: float, name: str, groups=None):
+    """The gradient parity rule for every group: the norm-wise relative error
+    is at most rtol, and every component satisfies
+    |gpu - ref| <= rtol (|ref| + 0.01 RMS(ref over the group)).
+    Logs every group before asserting."""
+    groups = list(ref) if groups is None else list(groups)
+    fails = []
+    for f in groups:
+        rel, cos = group_errors(gpu[f], ref[f])
+        frac, ratio = componentwise_ok(gpu[f], ref[f], rtol)
+        log(f"[{name}] {f:10s} rel {rel:.2e} cos {cos:.9f} fail {frac:.4f} worst {ratio:.2f}")
+        if rel > rtol or frac > 0:
+            fails.append((f, rel, frac, ratio))
+    assert not fails, f"{name}: {fails}"

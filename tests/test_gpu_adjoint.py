@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import componentwise_ok, group_errors, log, require_gpu
+from gpu_util import assert_grads, group_errors, log, require_gpu
 from paper_2609_08722_amd import api, synth
 
 pytestmark = pytest.mark.gpu
@@ -34,14 +34,7 @@ def l2_seed(orc, prog, target, W, H, tau=1e-3, tau_c=1.0):
 
 
 def compare(g, r, rtol, name, groups=GROUPS):
-    worst = 0.0
-    for f in groups:
-        rel, cos = group_errors(g[f], r[f])
-        frac, ratio = componentwise_ok(g[f], r[f], rtol)
-        log(f"[{name}] {f:10s} rel {rel:.2e} cos {cos:.9f} fail {frac:.4f} worst {ratio:.2f}")
-        worst = max(worst, ratio)
-        assert rel <= rtol, f
-    return worst
+    assert_grads(g, r, rtol, name, groups)
 
 
 def target_of(orc, w, seed):

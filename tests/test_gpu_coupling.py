@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import group_errors, hard_parity, log, require_gpu
+from gpu_util import assert_grads, hard_parity, log, require_gpu
 from paper_2609_08722_amd import _lib as L
 from paper_2609_08722_amd import api, synth
 
@@ -84,10 +84,7 @@ def orc_grads(orc, prog, coup, W, H, seed_rgb, tau_c=1.0):
 
 
 def compare(g, r, rtol, name):
-    for f in GROUPS:
-        rel, cos = group_errors(g[f], r[f])
-        log(f"[coupled {name}] {f:10s} rel {rel:.2e} cos {cos:.9f}")
-        assert rel <= rtol, f
+    assert_grads(g, r, rtol, f"coupled {name}", GROUPS)
 
 
 def test_adjoint_small(orc):

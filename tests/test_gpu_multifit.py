@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import group_errors, log, require_gpu
+from gpu_util import assert_grads, log, require_gpu
 from paper_2609_08722_amd import api, synth
 
 pytestmark = pytest.mark.gpu
@@ -60,15 +60,12 @@ def test_batch_mix_kernels_match_oracle_on_samples(orc):
         g = api.render_backward(dp, out["tape"], full)
         r = orc.backward(prog, w.width, w.height, seed.astype(np.float32).astype(np.float64),
                          tau_c=1.0, pixels=pix)
-        errs = {}
-        for q, f in enumerate(api.GEOM):
-            errs[f] = group_errors(g[f].cpu().numpy(), r["geom"][q])[0]
-        errs["logits"] = group_errors(g["logits"].cpu().numpy(), r["logits"])[0]
-        errs["palette"] = group_errors(g["palette"].cpu().numpy(), r["palette"])[0]
-        log(f"[{w.name}] soft max err {ferr:.2e}; records {out['tape'].max_records}; "
-            f"grad rel errs {' '.join(f'{k}={v:.1e}' for k, v in errs.items())}")
+        refg = {f: r["geom"][q] for q, f in enumerate(api.GEOM)}
+        refg["logits"], refg["palette"] = r["logits"], r["palette"]
+        got = {f: g[f].cpu().numpy() for f in refg}
+        log(f"[{w.name}] soft max err {ferr:.2e}; records {out['tape'].max_records}")
         assert ferr <= 1e-4
-        assert max(errs.values()) <= 1e-3
+        assert_grads(got, refg, 1e-3, w.name)
 
 
 def test_overflowing_job_skips_only_its_own_update():

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import group_errors, hard_parity, log, require_gpu
+from gpu_util import assert_grads, hard_parity, log, require_gpu
 from paper_2609_08722_amd import _lib as L
 from paper_2609_08722_amd import api, synth
 
@@ -82,10 +82,7 @@ def orc_grads(orc, prog, W, H, seed_rgb, tau_c=1.0):
 
 
 def compare(g, r, name):
-    for f in GROUPS:
-        rel, cos = group_errors(g[f], r[f])
-        log(f"[inert {name}] {f:10s} rel {rel:.2e} cos {cos:.9f}")
-        assert rel <= 1e-3, f
+    assert_grads(g, r, 1e-3, f"inert {name}", GROUPS)
 
 
 @pytest.mark.parametrize("ckpt", [8, 256])

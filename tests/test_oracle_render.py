@@ -191,3 +191,46 @@ def test_pixel_subset_matches_full(orc):
     sub = orc.render(prog, W, H, pixels=pix)
     for k in ("soft", "hard", "label", "owner", "dmin", "n_rec"):
         assert np.array_equal(sub[k], full[k][pix]), k
+
+
+def test_inert_dmin_is_textbook_minimum_over_visited_strokes(orc):
+    """The hard trace's boundary distance (the quantity that exempts a pixel
+    from hard-label parity, a pixel within 1e-5 of a closed footprint's edge,
+    Sec. 3): with transport off the point stays put, so it is the minimum of
+    |dist(x, segment_i) - r_i| over the strokes the trace visits, N-1 down to
+    the owner (all of them when no stroke owns the pixel)."""
+    W = H = 40
+    prog = small_program(n=45, seed=17)
+    out = orc.render(prog, W, H, transport=False)
+    pts = tb.pixel_centres(W, H)
+    want = np.full(len(pts), np.inf)
+    done = np.zeros(len(pts), bool)
+    for i in range(len(prog["cx"]) - 1, -1, -1):
+        g = [prog[k][i] for k in ("cx", "cy", "angle", "length", "half_width")]
+        d = tb.seg_distance(g, pts)
+        want = np.where(done, want, np.minimum(want, np.abs(d - g[4])))
+        done |= d <= g[4]
+    assert np.max(np.abs(out["dmin"] - want)) <= 1e-14
+    # an owner-step-only minimum, or one over every stroke, would differ
+    assert np.any(out["owner"] == -1) and np.any(out["owner"] >= 0)
+
+
+def test_drops_dmin_follows_the_textbook_chain(orc):
+    """With transport on, a drops-only program's boundary distance is the
+    minimum of ||x_i - c_i| - r_i| along the chain of classical drop maps,
+    up to the first hit."""
+    W = H = 40
+    dist = synth.StrokeDist(p_drop=1.0, r_lo=0.02, r_hi=0.06)
+    prog = small_program(n=60, dist=dist, seed=9)
+    out = orc.render(prog, W, H)
+    pts = tb.pixel_centres(W, H)
+    want = np.full(len(pts), np.inf)
+    done = np.zeros(len(pts), bool)
+    for i in range(len(prog["cx"]) - 1, -1, -1):
+        c = np.array([prog["cx"][i], prog["cy"][i]])
+        r = prog["half_width"][i]
+        d = np.linalg.norm(pts - c, axis=1)
+        want = np.where(done, want, np.minimum(want, np.abs(d - r)))
+        done |= d <= r
+        pts = tb.drop_backward(c, r, pts, floor_c=(1e-3 * r) ** 2)
+    assert np.max(np.abs(out["dmin"] - want)) <= 1e-12
