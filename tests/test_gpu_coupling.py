@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import assert_grads, hard_parity, log, require_gpu
+from gpu_util import assert_grads, hard_parity, log, require_gpu, rounding_envelope
 from paper_2609_08722_amd import _lib as L
 from paper_2609_08722_amd import api, synth
 
@@ -83,8 +83,8 @@ def orc_grads(orc, prog, coup, W, H, seed_rgb, tau_c=1.0):
     return out
 
 
-def compare(g, r, rtol, name):
-    assert_grads(g, r, rtol, f"coupled {name}", GROUPS)
+def compare(g, r, rtol, name, envelope=None):
+    assert_grads(g, r, rtol, f"coupled {name}", GROUPS, envelope=envelope)
 
 
 def test_adjoint_small(orc):
@@ -112,7 +112,13 @@ def test_adjoint_256_n500(orc):
     seed = 2.0 * (R - target) / R.size
     g, out = gpu_grads(prog, coup, w.width, w.height, seed, tau_c=w.tau_c, ckpt=w.ckpt)
     log(f"[coupled {w.name}] side-table records: max {out['tape'].max_records}")
-    compare(g, orc_grads(orc, prog, coup, w.width, w.height, seed, tau_c=w.tau_c), 1e-3, w.name)
+    ref = orc_grads(orc, prog, coup, w.width, w.height, seed, tau_c=w.tau_c)
+    # the coupled map is steeper near its deposits: one FP32 rounding of the
+    # program moves some of the oracle's own components by up to ~90x the
+    # 1e-3 allowance, so that change is the allowance there
+    env = rounding_envelope(prog, lambda p: orc_grads(orc, p, coup, w.width, w.height, seed,
+                                                      tau_c=w.tau_c), ref)
+    compare(g, ref, 1e-3, w.name, envelope=env)
 
 
 def test_fit_step_equals_decomposed_path():

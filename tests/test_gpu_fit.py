@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import assert_grads, group_errors, hard_parity, log, require_gpu
+from gpu_util import assert_grads, hard_parity, log, require_gpu, rounding_envelope
 from paper_2609_08722_amd import api, synth
 
 pytestmark = pytest.mark.gpu
@@ -124,14 +124,22 @@ def test_benchmark_workload_fit_step_matches_oracle_on_samples(orc):
     diff = R[ipix].cpu().numpy().astype(np.float64) - target[ipix].cpu().numpy()
     seed = 2.0 * diff / (3.0 * P)
     assert abs(loss - float(np.sum(diff ** 2)) / (3.0 * P)) <= 1e-5 * loss
-    r = orc.backward(prog, W, H, seed, tau=w.tau, tau_c=w.tau_c, eps=w.eps, pixels=pix)
-    refg = {f: r["geom"][q] for q, f in enumerate(api.GEOM)}
-    refg["logits"], refg["palette"] = r["logits"], r["palette"]
+    def grads_of(p):
+        r = orc.backward(p, W, H, seed, tau=w.tau, tau_c=w.tau_c, eps=w.eps, pixels=pix)
+        out = {f: r["geom"][q] for q, f in enumerate(api.GEOM)}
+        out["logits"], out["palette"] = r["logits"], r["palette"]
+        return out
+
+    refg = grads_of(prog)
+    # on 4096 sampled pixels a component is a few pixels' sum: where one FP32
+    # rounding of the program moves the oracle's own component by more than
+    # 1e-3 relative, that change is the allowance
+    env = rounding_envelope(prog, grads_of, refg)
     log(f"[{w.name}] soft max err {ferr.max():.2e}; hard exempt {exempt} of {len(pix)}, "
         f"mismatches {bad}")
     assert ferr.max() <= 1e-4
     assert bad == 0
-    assert_grads(got, refg, 1e-3, w.name)
+    assert_grads(got, refg, 1e-3, w.name, envelope=env)
 
 
 def test_side_table_overflow_skips_the_update_and_retry_is_exact():
