@@ -198,6 +198,22 @@ tbr_status tbr_render(const tbr_program* prog, const tbr_render_opts* opts, int3
                       float* rgb, int32_t* label, int32_t* owner, void* workspace,
                       size_t workspace_bytes, int32_t with_tape, void* stream);
 
+/* Allocation-free forward render, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): tbr_render without a tape and without a workspace
+ * argument. The prepared stroke records (and the coupled transport's profile
+ * coefficients) go to a 1 MiB array that the library holds in device memory,
+ * one per device, until the process ends; the call itself allocates nothing
+ * and calls no allocating routine. Arguments, outputs and results are those
+ * of tbr_render(prog, opts, mode, rgb, label, owner, ws, ws_bytes, 0, stream),
+ * bitwise. TBR_E_CAPACITY if n_strokes > TBR_STATIC_MAX_STROKES. Every call
+ * on one device shares that device's array: calls whose executions overlap
+ * on one device (different streams, or other host threads) race and give
+ * undefined results; calls ordered on one stream do not. */
+#define TBR_STATIC_MAX_STROKES 8192
+tbr_status tbr_render_static(const tbr_program* prog, const tbr_render_opts* opts, int32_t mode,
+                             float* rgb, int32_t* label, int32_t* owner, void* stream);
+
 /* Largest number of side-table records any pixel needed in the last taped
  * render of this workspace. SYNCHRONISES the stream. Returns TBR_E_OVERFLOW
  * when it exceeds opts->side_slots (the tape is then incomplete and the

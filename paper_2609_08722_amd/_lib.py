@@ -12,6 +12,7 @@ TBR_OK, TBR_PENDING = 0, 1
 TBR_E_INVALID, TBR_E_NOMEM, TBR_E_OVERFLOW, TBR_E_CAPACITY = -1, -2, -3, -4
 TBR_E_DEVICE, TBR_E_CANCELLED, TBR_E_NOTFOUND = -5, -6, -7
 TBR_HARD, TBR_SOFT = 1, 2
+TBR_STATIC_MAX_STROKES = 8192  # tbr_render_static's stroke limit
 TBR_TRANSPORT_CAPSULE, TBR_TRANSPORT_COUPLED, TBR_TRANSPORT_INERT, TBR_TRANSPORT_DROPS16 = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "TBR_OK", 1: "TBR_PENDING", -1: "TBR_E_INVALID", -2: "TBR_E_NOMEM",
@@ -97,6 +98,7 @@ _vp, _sz, _i32 = C.c_void_p, C.c_size_t, C.c_int32
 SIGNATURES = {
     "tbr_render_workspace_bytes": (_sz, [_vp, _i32, _i32, _i32]),
     "tbr_render": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _i32, _vp]),
+    "tbr_render_static": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "tbr_tape_records": (_i32, [_vp, _sz, _vp, _i32, _vp, _vp]),
     "tbr_backward_workspace_bytes": (_sz, [_vp, _i32, _i32]),
     "tbr_render_backward": (_i32, [_vp, _vp, _vp, _sz, _vp, _vp, _vp, _sz, _vp]),

@@ -174,6 +174,26 @@ def render(prog: dict, opts: Opts, mode: str = "soft", tape: bool = False,
         return out
 
 
+def render_static(prog: dict, opts: Opts, mode: str = "soft") -> dict:
+    """Forward render through tbr_render_static, which allocates nothing: no
+    tape, no workspace (the library's per-device scratch holds the stroke
+    records). Same outputs as render(prog, opts, mode)."""
+    lib = L.load()
+    cp = c_program(prog)
+    flags = {"soft": L.TBR_SOFT, "hard": L.TBR_HARD, "both": L.TBR_SOFT | L.TBR_HARD}[mode]
+    dev = prog["cx"].device
+    H, W = opts.height, opts.width
+    co = opts.c(cp.n_strokes)
+    rgb = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    label = owner = None
+    if flags & L.TBR_HARD:
+        label = torch.empty((H, W), dtype=torch.int32, device=dev)
+        owner = torch.empty((H, W), dtype=torch.int32, device=dev)
+    L.check(lib.tbr_render_static(C.byref(cp), C.byref(co), flags, _ptr(rgb), _ptr(label),
+                                  _ptr(owner), _stream()))
+    return {"rgb": rgb, "label": label, "owner": owner}
+
+
 def render_backward(prog: dict, tape: Tape, grad_rgb: torch.Tensor) -> dict:
     """Replay adjoint: gradients of sum(grad_rgb * R) w.r.t. every program
     array (same shapes as the program)."""

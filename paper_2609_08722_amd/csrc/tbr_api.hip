@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -418,34 +419,26 @@ tbr_status fit_core(int32_t n_strokes, int32_t n_palette, float* params, float* 
   return TBR_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t tbr_render_workspace_bytes(const tbr_render_opts* opts, int32_t n_strokes, int32_t mode,
-                                  int32_t with_tape) {
-  if (!opts || n_strokes < 0) return 0;
-  return render_layout(opts, n_strokes, with_tape && (mode & TBR_SOFT)).total;
-}
-
-tbr_status tbr_render(const tbr_program* prog, const tbr_render_opts* opts, int32_t mode,
-                      float* rgb, int32_t* label, int32_t* owner, void* workspace,
-                      size_t workspace_bytes, int32_t with_tape, void* stream) {
+tbr_status check_render(const tbr_program* prog, const tbr_render_opts* opts, int32_t mode,
+                        bool tape) {
   tbr_status s;
   if ((s = check_prog(prog))) return s;
   const bool soft = mode & TBR_SOFT, hard = mode & TBR_HARD;
   if (!(soft || hard) || (mode & ~(TBR_SOFT | TBR_HARD)))
     return fail(TBR_E_INVALID, "mode %d is not TBR_SOFT and/or TBR_HARD", mode);
-  if (with_tape && !soft) return fail(TBR_E_INVALID, "a tape needs TBR_SOFT");
-  if ((s = check_opts(opts, soft, with_tape != 0))) return s;
-  if (!workspace) return fail(TBR_E_INVALID, "workspace is NULL");
-  RenderLayout L = render_layout(opts, prog->n_strokes, with_tape != 0);
-  if (workspace_bytes < L.total)
-    return fail(TBR_E_INVALID, "workspace %zu bytes < required %zu", workspace_bytes, L.total);
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  char* ws = static_cast<char*>(workspace);
+  if (tape && !soft) return fail(TBR_E_INVALID, "a tape needs TBR_SOFT");
+  return check_opts(opts, soft, tape);
+}
+
+// Stroke preparation and the trace kernels of one render, on the records,
+// status word, profile cubics and tape that layout L places in ws.
+tbr_status render_launch(const tbr_program* prog, const tbr_render_opts* opts, int32_t mode,
+                         float* rgb, int32_t* label, int32_t* owner, char* ws,
+                         const RenderLayout& L, bool tape, hipStream_t st) {
+  tbr_status s;
+  const bool soft = mode & TBR_SOFT, hard = mode & TBR_HARD;
   StrokeRec* recs = reinterpret_cast<StrokeRec*>(ws + L.recs);
-  KTape t = ktape(ws, L, opts, with_tape != 0);
+  KTape t = ktape(ws, L, opts, tape);
   float4* coup = coup_of(ws, L, opts);
   if ((s = launch_prep(prog, opts, recs, t.status, coup, st))) return s;
   dim3 grid(tiles_x(opts), tiles_y(opts));
@@ -499,6 +492,75 @@ tbr_status tbr_render(const tbr_program* prog, const tbr_render_opts* opts, int3
     if ((s = check_launch("trace_hard"))) return s;
   }
   return TBR_OK;
+}
+
+
+// The allocation-free render (tbr_render_static) keeps its prepared stroke
+// records, status word and profile cubics in this array instead of a
+// workspace: one copy per device, held until the process ends. Host code
+// uses only the per-device address from hipGetSymbolAddress.
+constexpr size_t kScratchBytes = size_t(1) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_dev[kMaxDevices];
+
+// The address of `scratch` on the current device, looked up once per device.
+tbr_status scratch_here(char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(TBR_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(TBR_E_DEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(TBR_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return TBR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tbr_render_workspace_bytes(const tbr_render_opts* opts, int32_t n_strokes, int32_t mode,
+                                  int32_t with_tape) {
+  if (!opts || n_strokes < 0) return 0;
+  return render_layout(opts, n_strokes, with_tape && (mode & TBR_SOFT)).total;
+}
+
+tbr_status tbr_render(const tbr_program* prog, const tbr_render_opts* opts, int32_t mode,
+                      float* rgb, int32_t* label, int32_t* owner, void* workspace,
+                      size_t workspace_bytes, int32_t with_tape, void* stream) {
+  tbr_status s;
+  if ((s = check_render(prog, opts, mode, with_tape != 0))) return s;
+  if (!workspace) return fail(TBR_E_INVALID, "workspace is NULL");
+  RenderLayout L = render_layout(opts, prog->n_strokes, with_tape != 0);
+  if (workspace_bytes < L.total)
+    return fail(TBR_E_INVALID, "workspace %zu bytes < required %zu", workspace_bytes, L.total);
+  return render_launch(prog, opts, mode, rgb, label, owner, static_cast<char*>(workspace), L,
+                       with_tape != 0, reinterpret_cast<hipStream_t>(stream));
+}
+
+tbr_status tbr_render_static(const tbr_program* prog, const tbr_render_opts* opts, int32_t mode,
+                             float* rgb, int32_t* label, int32_t* owner, void* stream) {
+  tbr_status s;
+  if ((s = check_render(prog, opts, mode, false))) return s;
+  if (prog->n_strokes > TBR_STATIC_MAX_STROKES)
+    return fail(TBR_E_CAPACITY, "n_strokes = %d exceeds the allocation-free render's %d",
+                prog->n_strokes, TBR_STATIC_MAX_STROKES);
+  RenderLayout L = render_layout(opts, prog->n_strokes, false);
+  if (L.total > kScratchBytes)
+    return fail(TBR_E_CAPACITY, "scratch %zu bytes < required %zu", kScratchBytes, L.total);
+  char* ws = nullptr;
+  if ((s = scratch_here(&ws))) return s;
+  return render_launch(prog, opts, mode, rgb, label, owner, ws, L, false,
+                       reinterpret_cast<hipStream_t>(stream));
 }
 
 tbr_status tbr_tape_records(const void* workspace, size_t workspace_bytes,
