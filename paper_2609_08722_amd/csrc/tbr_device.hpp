@@ -71,18 +71,13 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 __device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float hw_exp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
 
-// atan(a) for a in [0, 1].
+// atan(a) for a in [0, 1] (Horner's rule in a^2).
+constexpr int kAtanTerms = sizeof(kAtan) / sizeof(kAtan[0]);
 __device__ __forceinline__ float atan01(float a) {
-  float u = a * a;
-  float p = kAtan[8];
-  p = fmaf(p, u, kAtan[7]);
-  p = fmaf(p, u, kAtan[6]);
-  p = fmaf(p, u, kAtan[5]);
-  p = fmaf(p, u, kAtan[4]);
-  p = fmaf(p, u, kAtan[3]);
-  p = fmaf(p, u, kAtan[2]);
-  p = fmaf(p, u, kAtan[1]);
-  p = fmaf(p, u, kAtan[0]);
+  const float u = a * a;
+  float p = kAtan[kAtanTerms - 1];
+#pragma unroll
+  for (int j = kAtanTerms - 2; j >= 0; --j) p = fmaf(p, u, kAtan[j]);
   return a * p;
 }
 
@@ -114,8 +109,11 @@ struct Chart {
   float w;         // arclength fraction from the flank midpoint, [0, 1/4]
 };
 
-__device__ __forceinline__ Chart chart(double x, double y, const StrokeRec& g) {
-  Chart c;
+// The chart in two parts: the distance (all a far vote needs), then the
+// angle, fraction and reciprocals. kFar: the point is known to lie off the
+// segment (sigma > 0, as beyond a stroke's far margin), so no reciprocal
+// needs a floor and cos th needs no select.
+__device__ __forceinline__ void chart_dist(double x, double y, const StrokeRec& g, Chart& c) {
   float dx = (float)(x - g.mx), dy = (float)(y - g.my);
   // The inner products take + 0, so s and h are never -0 and each fold sign,
   // one bit insert, is sgn with sgn(0) = +1.
@@ -127,15 +125,36 @@ __device__ __forceinline__ Chart chart(double x, double y, const StrokeRec& g) {
   c.H = fabsf(c.h);
   c.E = fmaxf(c.S - g.hl, 0.f);
   c.sig = hw_sqrt(fmaf(c.H, c.H, c.E * c.E));
-  c.th = atan2_q1(c.E, c.H);
-  // on the segment E = 0, so the floored reciprocal gives sin th = 0
-  c.inv_sig = rcp(fmaxf(c.sig, kMinNormal));
-  c.sn = c.E * c.inv_sig;
-  c.cs = c.sig > 0.f ? c.H * c.inv_sig : 1.f;
-  float t = fmaf(c.sig, c.th, fminf(c.S, g.hl));  // arclength from the flank midpoint
-  c.per = fmaf(kTwoPi, c.sig, g.two_ell);          // P_l(sigma)
-  c.inv_per = rcp(fmaxf(c.per, kMinNormal));
-  c.w = t * c.inv_per;                               // drop centre: t = 0, w = 0
+}
+
+template <bool kFar = false>
+__device__ __forceinline__ void chart_angle(const StrokeRec& g, Chart& c) {
+  if constexpr (kFar) {
+    const float hi = fmaxf(c.E, c.H), lo = fminf(c.E, c.H);
+    const float t = atan01(lo * rcp(hi));
+    c.th = c.E > c.H ? kHalfPi - t : t;
+    c.inv_sig = rcp(c.sig);
+    c.sn = c.E * c.inv_sig;
+    c.cs = c.H * c.inv_sig;
+    c.per = fmaf(kTwoPi, c.sig, g.two_ell);
+    c.inv_per = rcp(c.per);
+  } else {
+    c.th = atan2_q1(c.E, c.H);
+    // on the segment E = 0, so the floored reciprocal gives sin th = 0
+    c.inv_sig = rcp(fmaxf(c.sig, kMinNormal));
+    c.sn = c.E * c.inv_sig;
+    c.cs = c.sig > 0.f ? c.H * c.inv_sig : 1.f;
+    c.per = fmaf(kTwoPi, c.sig, g.two_ell);           // P_l(sigma)
+    c.inv_per = rcp(fmaxf(c.per, kMinNormal));
+  }
+  const float t = fmaf(c.sig, c.th, fminf(c.S, g.hl));  // arclength from the flank midpoint
+  c.w = t * c.inv_per;                                  // drop centre: t = 0, w = 0
+}
+
+__device__ __forceinline__ Chart chart(double x, double y, const StrokeRec& g) {
+  Chart c;
+  chart_dist(x, y, g, c);
+  chart_angle(g, c);
   return c;
 }
 
@@ -341,6 +360,36 @@ __device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, boo
   m.dcos = dcos;
   flank_part(c, g, m);
   return m;
+}
+
+// psi of a point beyond the stroke's far margin (no floor, uniform
+// insertion), displacement only, for the forward traces' far steps. psi
+// moves a point along its leaf towards the segment, so a point on a cap
+// either stays on it (th + dth > 0 with the cap-to-cap dth) or reaches the
+// flank; a wave whose lanes all stay takes the cap-to-cap formulas alone.
+__device__ __forceinline__ Move psi_far(const Chart& c, const StrokeRec& g, const Leaf& lf) {
+  const float two_ell = g.two_ell;
+  const float q = back_area(c.sig, lf, two_ell);
+  const float sig_o = area_to_dist(q, g);
+  const float dsig = -lf.ar * rcp(fmaf(kPi, c.sig + sig_o, two_ell));
+  const float inv_sig_o = rcp(sig_o);
+  const float dth_cc = dsig * g.ell * (kPi - 2.f * c.th) * (c.inv_per * inv_sig_o);
+  if (wave_all(c.th > 0.f && c.th + dth_cc > 0.f)) {
+    Move m;
+    float sd, cdm1;
+    if (wave_all(fabsf(dth_cc) < kSmallTurn)) {
+      sincosm1_small(dth_cc, sd, cdm1);
+    } else {
+      sincosm1(dth_cc, sd, cdm1);
+    }
+    const float dsin = fmaf(c.sn, cdm1, c.cs * sd);
+    const float dcos = fmaf(c.cs, cdm1, -(c.sn * sd));
+    m.dS = fmaf(dsig, c.sn + dsin, c.sig * dsin);
+    m.dH = fmaf(dsig, c.cs + dcos, c.sig * dcos);
+    m.floored = false;
+    return m;
+  }
+  return displace<false, false>(c, g, true, lf);
 }
 
 // Phi of a charted point with 1 / P_l(sig_o), for the replay's common steps:

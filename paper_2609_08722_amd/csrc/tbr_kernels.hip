@@ -196,7 +196,7 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
     if constexpr (kT == kDrops) {
       drops_backward(x, y, g);  // R_D: rendered only, no tape
     } else if constexpr (kT != kInert) {
-      Move mv = displace<false, kFloor>(c, g, true, lf);
+      Move mv = kFloor ? displace<false, true>(c, g, true, lf) : psi_far(c, g, lf);
       if constexpr (kFloor) {  // record where the floor binds
         if (mv.floored) {
           if (write_tape && nrec < tape.side_slots) {
@@ -231,11 +231,22 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
         }
         next_ck -= k;
       }
-      c = chart(x, y, g);
-      lf = leaf_at<kT == kCoupled>(c, g, coup, i);
-      if (!wave_all(is_far<kT == kCoupled>(c.sig, lf, g))) {
-        near = true;
-        break;
+      if constexpr (kT == kCoupled) {  // the far vote needs the leaf's edge
+        c = chart(x, y, g);
+        lf = leaf_at<true>(c, g, coup, i);
+        if (!wave_all(is_far<true>(c.sig, lf, g))) {
+          near = true;
+          break;
+        }
+      } else {
+        lf = uniform_leaf(g);
+        chart_dist(x, y, g, c);
+        if (!wave_all(is_far<false>(c.sig, lf, g))) {
+          chart_angle(g, c);
+          near = true;
+          break;
+        }
+        if constexpr (kT == kCapsule) chart_angle<true>(g, c);
       }
       transport(i, c, g, lf, std::integral_constant<bool, false>{});
     }
@@ -282,16 +293,25 @@ __device__ __forceinline__ void hard_pixel(const StrokeRec* __restrict__ recs,
     if (wave_all(done)) break;
     const StrokeRec g = load_rec(recs, i);
     if (!done) {
-      Chart c = chart(x, y, g);
-      const Leaf lf = leaf_at<kT == kCoupled>(c, g, coup, i);
+      Chart c;
+      Leaf lf;
+      if constexpr (kT == kCoupled) {
+        c = chart(x, y, g);
+        lf = leaf_at<true>(c, g, coup, i);
+      } else {
+        lf = uniform_leaf(g);
+        chart_dist(x, y, g, c);
+      }
       if constexpr (kT == kCapsule || kT == kCoupled) {
         // Every lane still tracing lies beyond the stroke's far margin: none
         // can hit it, and psi's floor cannot bind there.
         if (wave_all(is_far<kT == kCoupled>(c.sig, lf, g))) {
-          advance(x, y, c, displace<false, false>(c, g, true, lf), g);
+          if constexpr (kT == kCapsule) chart_angle<true>(g, c);
+          advance(x, y, c, psi_far(c, g, lf), g);
           continue;
         }
       }
+      if constexpr (kT != kCoupled) chart_angle(g, c);
       if (c.sig <= lf.r) {  // closed footprint
         done = true;
         own = i;
@@ -630,9 +650,18 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
         const int i = c0 + j;  // stroke index (0-based); its input state is x_{i+1}
         g = load_rec(recs, i);
         if (i == next_ck || wave_any(top_idx == i)) break;
-        Chart ca = chart(x, y, g);
-        const Leaf lf = leaf_at<kC>(ca, g, coup, i);
-        if (!wave_all(is_far<kC>(ca.sig, lf, g))) break;
+        Chart ca;
+        Leaf lf;
+        if constexpr (kC) {  // the far vote needs the leaf's edge
+          ca = chart(x, y, g);
+          lf = leaf_at<true>(ca, g, coup, i);
+          if (!wave_all(is_far<true>(ca.sig, lf, g))) break;
+        } else {
+          lf = uniform_leaf(g);
+          chart_dist(x, y, g, ca);
+          if (!wave_all(is_far<false>(ca.sig, lf, g))) break;
+          chart_angle<true>(g, ca);
+        }
         Move mv = regenerate(ca, g, lf);
         // unfolded displacement; psi runs from the regenerated x_i back to
         // the chart point x_{i-1}, so its increments are Phi's negated
