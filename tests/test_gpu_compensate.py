@@ -4,10 +4,12 @@ up to 2000 strokes.
 
 Blocked chains are chaotic: a clamp into a later footprint can land points
 of different strokes on top of one another, and a later clamp of a point
-lying on a segment has no defined side (or, at a drop, direction). The
-parity asked is therefore step-wise: each stroke, pre-imaged by the oracle
-through the GPU's own compensated later strokes, must match the GPU's
-stroke; strokes whose chain passed within 1e-5 of a footprint edge,
+lying on a segment has no defined side (or, at a drop, direction). On a
+sparse program (test_sparse_2000_end_to_end) the parity is end to end: the
+oracle compensates the inert program alone, and every stroke whose chain
+is clean in the oracle's own pass must match. On the dense programs it is
+step-wise: each stroke, pre-imaged by the oracle through the GPU's own
+compensated later strokes, must match the GPU's stroke; strokes whose chain passed within 1e-5 of a footprint edge,
 clamped a point within 1e-6 of a segment, or grows an error more than
 100-fold from some step to its end (the oracle's Jacobian products), are
 exempt (their counts are logged), as are hard labels near an edge. Unblocked strokes must also
@@ -123,3 +125,35 @@ def test_edge_cases(orc):
     check(orc, drops, True, False, "drops")
     out, _ = api.compensate(api.to_device(drops), endpoint=True)
     assert float(out["length"].abs().max()) <= 1e-7
+
+
+SPARSE = synth.StrokeDist(p_drop=0.3, len_lo=0.0, len_hi=0.04, r_lo=0.001, r_hi=0.008)
+
+
+@pytest.mark.parametrize("endpoint", [False, True])
+@pytest.mark.parametrize("skip", [False, True])
+def test_sparse_2000_end_to_end(orc, endpoint, skip):
+    """2000 strokes small enough that most chains stay clear of later
+    footprints (about a fifth still has a blocked step): the oracle's
+    compensation of the inert program alone, its clean mask from its own
+    chains, and every clean stroke's two ends within 1e-5 of the GPU's."""
+    require_gpu()
+    prog = synth.make_program(2000, 4, 50, SPARSE, beta=2.0)
+    out, blocked = api.compensate(api.to_device(prog), endpoint=endpoint, skip_blocked=skip)
+    got = {f: out[f].cpu().numpy().astype(np.float64) for f in FIELDS}
+    gb = blocked.cpu().numpy()
+    ref, rb, dmin, smin, amp = orc.compensate(prog, endpoint=endpoint, skip=skip,
+                                              with_dmin=True, with_amp=True)
+    clean = (dmin >= 1e-5) & (smin >= 1e-6) & (amp <= 100)
+    n = len(gb)
+    ge = ends({**got, "length": got["length"]}, np.arange(n), True)
+    re_ = ends({f: np.asarray(ref[f], np.float64) for f in FIELDS}, np.arange(n), True)
+    dend = np.max([np.abs(a - b).max(1) for a, b in zip(ge, re_)], axis=0)
+    log(f"[compensate sparse 2000 endpoint={endpoint} skip={skip}] blocked "
+        f"{int((rb > 0).sum())}; clean {clean.mean():.4f}; clean ends max |d| "
+        f"{dend[clean].max(initial=0):.2e}, median {np.median(dend[clean]):.2e}; "
+        f"blocked counts equal on clean {np.array_equal(gb[clean], rb[clean])}")
+    assert (rb > 0).sum() >= 200
+    assert clean.mean() >= 0.9
+    assert np.array_equal(gb[clean], rb[clean])
+    assert dend[clean].max(initial=0) <= 1e-5
