@@ -425,9 +425,9 @@ def main():
                     help="skip the closed-form compensation pass")
     ap.add_argument("--no-transports", action="store_true",
                     help="skip the renders and fit steps under the other transports")
-    ap.add_argument("--serve-seconds", type=float, default=8.0,
-                    help="length of the Poisson serving replay (0 = skip)")
-    ap.add_argument("--serve-warmup", type=float, default=1.0,
+    ap.add_argument("--serve-seconds", type=float, default=65.0,
+                    help="length of the Poisson serving replay, warm-up included (0 = skip)")
+    ap.add_argument("--serve-warmup", type=float, default=5.0,
                     help="leading seconds of the serving trace left out of the statistics")
     ap.add_argument("--serve-rate", type=float, default=200.0,
                     help="Poisson arrival rate of the serving replay, requests/s")

@@ -358,8 +358,9 @@ void tbr_schedule_at(int32_t step, int32_t total_steps, float tau_first, float t
  *   1. retires launches that finished, freeing their requests' slots and
  *      arena bytes;
  *   2. admits queued requests in FIFO order while a slot is free and the
- *      arena can hold the request's prepared stroke records (its footprint,
- *      tbr_serve_request_bytes);
+ *      arena can hold the request's HBM footprint: its prepared stroke
+ *      records (tbr_serve_request_bytes) plus the outputs it asks the server
+ *      to hold in the arena (tbr_serve_output_bytes);
  *   3. packs all admitted requests into one persistent launch over
  *      (request, 16x16 tile) work items.
  * Each stream owns a hipGraph built at create time: one copy of the tick's
@@ -370,8 +371,11 @@ void tbr_schedule_at(int32_t step, int32_t total_steps, float tau_first, float t
  * Launches rotate over `streams` streams, so requests admitted while others
  * run overlap with them on the device. Every pixel is computed by the same
  * device code as tbr_render, so a request's result does not depend on what
- * else is in flight. Output buffers belong to the caller and must stay valid
- * until the ticket completes.
+ * else is in flight. An output is either caller memory, which must stay valid
+ * until the ticket completes, or held by the server in the arena
+ * (tbr_request.arena_outputs): then it counts towards the request's
+ * footprint from admission, its address comes with the completed poll, and
+ * it stays valid (its bytes stay taken) until tbr_serve_release.
  * ------------------------------------------------------------------------- */
 typedef struct tbr_server tbr_server;
 
@@ -384,7 +388,12 @@ typedef struct tbr_serve_opts {
   int32_t streams;                /* launches in flight at once, 1..4 */
   int32_t fake_device;            /* 1: host-only executor for scheduler tests; no GPU work */
   float fake_ns_per_pixel_stroke; /* fake executor: modelled cost per pixel-stroke */
+  int32_t fake_fail_launch;       /* fake executor: the 1-based launch that reports a device
+                                     error on completion (0: none); ignored on a GPU */
 } tbr_serve_opts;
+
+/* Outputs of a request that the server holds in its arena. */
+enum { TBR_OUT_RGB = 1, TBR_OUT_LABEL = 2, TBR_OUT_OWNER = 4, TBR_OUT_ALL = 7 };
 
 typedef struct tbr_request {
   uint64_t program_id;            /* from tbr_serve_register_program */
@@ -395,12 +404,17 @@ typedef struct tbr_request {
   float* rgb;                     /* device [H*W*3]: soft composite, or hard colour (may be NULL for hard) */
   int32_t* label;                 /* hard: device [H*W] or NULL */
   int32_t* owner;                 /* hard: device [H*W] or NULL */
+  int32_t arena_outputs;          /* TBR_OUT_* mask of outputs held in the arena by the server
+                                     (their pointers above must be NULL; soft: TBR_OUT_RGB only) */
 } tbr_request;
 
 typedef struct tbr_result {
   int32_t status;                 /* TBR_OK, TBR_PENDING, TBR_E_CANCELLED or TBR_E_DEVICE */
   double t_submit, t_admit, t_start, t_done;  /* seconds on tbr_serve_now()'s clock */
   int64_t pixel_strokes;          /* width * height * n_strokes */
+  float* rgb;                     /* the request's outputs (device): the caller's pointers, or */
+  int32_t* label;                 /* for TBR_OUT_* ones the arena addresses once complete, */
+  int32_t* owner;                 /* valid until tbr_serve_release */
 } tbr_result;
 
 typedef struct tbr_serve_stats {
@@ -417,6 +431,10 @@ typedef struct tbr_serve_stats {
 size_t tbr_serve_program_bytes(int32_t n_strokes, int32_t n_palette);
 size_t tbr_serve_request_bytes(int32_t n_strokes);
 size_t tbr_serve_tick_bytes(const tbr_serve_opts* opts);
+/* Arena bytes of the outputs a request asks the server to hold (a TBR_OUT_*
+ * mask): 12 B per pixel for rgb, 4 B each for label and owner. 0 for a bad
+ * canvas or mask. */
+size_t tbr_serve_output_bytes(int32_t width, int32_t height, int32_t arena_outputs);
 
 /* Create a server (starts its scheduler thread). */
 tbr_status tbr_serve_create(const tbr_serve_opts* opts, tbr_server** server);
@@ -427,14 +445,25 @@ tbr_status tbr_serve_register_program(tbr_server* server, const tbr_program* pro
                                       uint64_t* program_id);
 
 /* Queue a request; returns at once with a ticket. TBR_E_CAPACITY when the
- * queue is full, TBR_E_NOMEM when the request could never be admitted,
- * TBR_E_NOTFOUND for an unknown program. */
+ * queue is full, TBR_E_NOMEM when the request's footprint exceeds the arena
+ * less its launch buffers and programs (it could never be admitted),
+ * TBR_E_NOTFOUND for an unknown program, TBR_E_INVALID for a bad canvas,
+ * relaxation, mode, output set or arena_outputs mask. */
 tbr_status tbr_serve_submit(tbr_server* server, const tbr_request* request, uint64_t* ticket);
 
-/* TBR_OK (request finished; its outputs are complete on the device) or
- * TBR_E_CANCELLED, after which the ticket is forgotten; TBR_PENDING while
- * queued or running. Fills *result in every case. Does not synchronise. */
+/* TBR_OK (request finished; its outputs are complete on the device),
+ * TBR_E_CANCELLED, or TBR_E_DEVICE (its launch failed), after which the ticket
+ * is forgotten, except that a finished request holding arena outputs keeps
+ * them (and its ticket) until tbr_serve_release; TBR_PENDING while queued or
+ * running. Fills *result in every case. Does not synchronise. */
 tbr_status tbr_serve_poll(tbr_server* server, uint64_t ticket, tbr_result* result);
+
+/* Give back a finished request's arena outputs (and forget its ticket) once
+ * the caller has consumed them: work of the caller's that reads them must be
+ * complete, since the bytes may be handed to the next admitted request at
+ * once. TBR_OK; TBR_PENDING while the request is queued or running;
+ * TBR_E_NOTFOUND for an unknown or forgotten ticket. */
+tbr_status tbr_serve_release(tbr_server* server, uint64_t ticket);
 
 /* Cancel a queued request (TBR_OK); an admitted one runs to completion
  * (TBR_PENDING). */

@@ -12,6 +12,7 @@ TBR_OK, TBR_PENDING = 0, 1
 TBR_E_INVALID, TBR_E_NOMEM, TBR_E_OVERFLOW, TBR_E_CAPACITY = -1, -2, -3, -4
 TBR_E_DEVICE, TBR_E_CANCELLED, TBR_E_NOTFOUND = -5, -6, -7
 TBR_HARD, TBR_SOFT = 1, 2
+TBR_OUT_RGB, TBR_OUT_LABEL, TBR_OUT_OWNER, TBR_OUT_ALL = 1, 2, 4, 7
 TBR_STATIC_MAX_STROKES = 8192  # tbr_render_static's stroke limit
 TBR_TRANSPORT_CAPSULE, TBR_TRANSPORT_COUPLED, TBR_TRANSPORT_INERT, TBR_TRANSPORT_DROPS16 = 0, 1, 2, 3
 
@@ -71,19 +72,21 @@ class FitJob(C.Structure):
 class ServeOpts(C.Structure):
     _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("max_slots", C.c_int32),
                 ("max_queue", C.c_int32), ("max_tick_items", C.c_int32), ("streams", C.c_int32),
-                ("fake_device", C.c_int32), ("fake_ns_per_pixel_stroke", C.c_float)]
+                ("fake_device", C.c_int32), ("fake_ns_per_pixel_stroke", C.c_float),
+                ("fake_fail_launch", C.c_int32)]
 
 
 class Request(C.Structure):
     _fields_ = [("program_id", C.c_uint64), ("mode", C.c_int32), ("width", C.c_int32),
                 ("height", C.c_int32), ("tau", C.c_float), ("tau_min", C.c_float),
                 ("tau_c", C.c_float), ("eps_floor", C.c_float), ("rgb", C.c_void_p),
-                ("label", C.c_void_p), ("owner", C.c_void_p)]
+                ("label", C.c_void_p), ("owner", C.c_void_p), ("arena_outputs", C.c_int32)]
 
 
 class Result(C.Structure):
     _fields_ = [("status", C.c_int32), ("t_submit", C.c_double), ("t_admit", C.c_double),
-                ("t_start", C.c_double), ("t_done", C.c_double), ("pixel_strokes", C.c_int64)]
+                ("t_start", C.c_double), ("t_done", C.c_double), ("pixel_strokes", C.c_int64),
+                ("rgb", C.c_void_p), ("label", C.c_void_p), ("owner", C.c_void_p)]
 
 
 class ServeStats(C.Structure):
@@ -119,11 +122,13 @@ SIGNATURES = {
     "tbr_serve_program_bytes": (_sz, [_i32, _i32]),
     "tbr_serve_request_bytes": (_sz, [_i32]),
     "tbr_serve_tick_bytes": (_sz, [_vp]),
+    "tbr_serve_output_bytes": (_sz, [_i32, _i32, _i32]),
     "tbr_serve_create": (_i32, [_vp, _vp]),
     "tbr_serve_register_program": (_i32, [_vp, _vp, _vp]),
     "tbr_serve_submit": (_i32, [_vp, _vp, _vp]),
     "tbr_serve_poll": (_i32, [_vp, C.c_uint64, _vp]),
     "tbr_serve_cancel": (_i32, [_vp, C.c_uint64]),
+    "tbr_serve_release": (_i32, [_vp, C.c_uint64]),
     "tbr_serve_get_stats": (_i32, [_vp, _vp]),
     "tbr_serve_destroy": (None, [_vp]),
     "tbr_serve_now": (C.c_double, []),

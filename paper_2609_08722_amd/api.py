@@ -420,20 +420,25 @@ class Server:
     are copied into it once. submit() returns a ticket at once; poll() says
     when the request's outputs are complete on the device."""
 
+    OUTS = {"rgb": L.TBR_OUT_RGB, "label": L.TBR_OUT_LABEL, "owner": L.TBR_OUT_OWNER}
+
     def __init__(self, arena_bytes: int = 256 << 20, max_slots: int = 64, max_queue: int = 4096,
                  max_tick_items: int = 1 << 17, streams: int = 3, fake_device: bool = False,
-                 fake_ns_per_pixel_stroke: float = 0.0, device="cuda"):
+                 fake_ns_per_pixel_stroke: float = 0.0, fake_fail_launch: int = 0,
+                 device="cuda"):
         lib = L.load()
         self.arena = None if fake_device else torch.empty(arena_bytes, dtype=torch.uint8,
                                                           device=device)
         self.opts = L.ServeOpts(_ptr(self.arena), int(arena_bytes), int(max_slots),
                                 int(max_queue), int(max_tick_items), int(streams),
-                                int(fake_device), float(fake_ns_per_pixel_stroke))
+                                int(fake_device), float(fake_ns_per_pixel_stroke),
+                                int(fake_fail_launch))
         h = C.c_void_p()
         L.check(lib.tbr_serve_create(C.byref(self.opts), C.byref(h)))
         self.h = h
         self.fake = fake_device
         self._keep = {}
+        self._shape = {}  # ticket -> (width, height, arena_outputs mask)
 
     def register(self, prog: dict) -> int:
         lib = L.load()
@@ -449,27 +454,63 @@ class Server:
         return pid.value
 
     def submit(self, program_id: int, mode: str, width: int, height: int, rgb=None, label=None,
-               owner=None, tau=1e-3, tau_min=0.0, tau_c=0.0, eps=1e-3) -> int:
+               owner=None, tau=1e-3, tau_min=0.0, tau_c=0.0, eps=1e-3,
+               arena_outputs=()) -> int:
+        """Queue a request. arena_outputs: names among 'rgb', 'label', 'owner'
+        that the server holds in its arena (counted in the request's
+        footprint; see poll and release)."""
         lib = L.load()
+        mask = 0
+        for name in arena_outputs:
+            mask |= self.OUTS[name]
         r = L.Request(int(program_id), L.TBR_SOFT if mode == "soft" else L.TBR_HARD, int(width),
                       int(height), float(tau), float(tau_min), float(tau_c), float(eps),
-                      _ptr(rgb), _ptr(label), _ptr(owner))
+                      _ptr(rgb), _ptr(label), _ptr(owner), mask)
         t = C.c_uint64()
         L.check(lib.tbr_serve_submit(self.h, C.byref(r), C.byref(t)))
+        if mask:
+            self._shape[t.value] = (int(width), int(height), mask)
         return t.value
 
+    def _view(self, ptr, nbytes, dtype, shape):
+        off = int(ptr) - self.arena.data_ptr()
+        return self.arena[off:off + nbytes].view(dtype).view(shape)
+
     def poll(self, ticket: int):
-        """None while pending; else a dict with status and timestamps."""
+        """None while pending; else a dict with status and timestamps, and
+        for arena outputs views of them into the arena ('rgb' [H,W,3],
+        'label', 'owner' [H,W]), valid until release(ticket)."""
         lib = L.load()
         res = L.Result()
         st = lib.tbr_serve_poll(self.h, C.c_uint64(ticket), C.byref(res))
         if st == L.TBR_PENDING:
             return None
         if st not in (L.TBR_OK, L.TBR_E_CANCELLED):
+            self._shape.pop(ticket, None)
             L.check(st)
-        return {"status": st, "t_submit": res.t_submit, "t_admit": res.t_admit,
-                "t_start": res.t_start, "t_done": res.t_done,
-                "pixel_strokes": res.pixel_strokes}
+        out = {"status": st, "t_submit": res.t_submit, "t_admit": res.t_admit,
+               "t_start": res.t_start, "t_done": res.t_done,
+               "pixel_strokes": res.pixel_strokes}
+        shp = self._shape.get(ticket)
+        if st == L.TBR_OK and shp and not self.fake:
+            W, H, mask = shp
+            if mask & L.TBR_OUT_RGB:
+                out["rgb"] = self._view(res.rgb, H * W * 12, torch.float32, (H, W, 3))
+            if mask & L.TBR_OUT_LABEL:
+                out["label"] = self._view(res.label, H * W * 4, torch.int32, (H, W))
+            if mask & L.TBR_OUT_OWNER:
+                out["owner"] = self._view(res.owner, H * W * 4, torch.int32, (H, W))
+        return out
+
+    def release(self, ticket: int) -> int:
+        """Give back a finished request's arena outputs; the caller's reads
+        of them must be complete (synchronise first)."""
+        st = L.load().tbr_serve_release(self.h, C.c_uint64(ticket))
+        if st not in (L.TBR_OK, L.TBR_PENDING):
+            L.check(st)
+        if st == L.TBR_OK:
+            self._shape.pop(ticket, None)
+        return st
 
     def cancel(self, ticket: int) -> int:
         return L.load().tbr_serve_cancel(self.h, C.c_uint64(ticket))

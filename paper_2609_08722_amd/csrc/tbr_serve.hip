@@ -7,7 +7,8 @@
 //   1. retires finished launches (their HIP event has completed), freeing
 //      the requests' arena bytes and slots,
 //   2. admits queued requests in order while a slot is free and the arena
-//      can hold the request's prepared stroke records (its HBM footprint),
+//      can hold the request's HBM footprint: its prepared stroke records,
+//      and the outputs it asked the server to hold (arena_outputs),
 //   3. packs every admitted-but-not-launched request into ONE persistent
 //      launch (k_serve) over a list of (request, 16x16 tile) work items.
 //      A tick is a captured hipGraph built once per stream: one copy of
@@ -119,13 +120,34 @@ struct Program {
   size_t off = 0, bytes = 0;  // arena copy: cx|cy|angle|length|half_width|logits|palette
 };
 
-enum ReqState { kQueued, kAdmitted, kRunning, kDone, kCancelled };
+enum ReqState { kQueued, kAdmitted, kRunning, kDone, kFailed, kCancelled };
+
+// Arena-held outputs of a request, in this order after its stroke records.
+struct OutLayout {
+  size_t rgb, label, owner, total;  // offsets from the outputs' start; total bytes
+};
+
+OutLayout out_layout(int width, int height, int32_t mask) {
+  OutLayout L{};
+  const size_t P = (size_t)width * height;
+  size_t off = 0;
+  L.rgb = off;
+  if (mask & TBR_OUT_RGB) off = align_up(off + P * 3 * sizeof(float));
+  L.label = off;
+  if (mask & TBR_OUT_LABEL) off = align_up(off + P * sizeof(int32_t));
+  L.owner = off;
+  if (mask & TBR_OUT_OWNER) off = align_up(off + P * sizeof(int32_t));
+  L.total = off;
+  return L;
+}
 
 struct Request {
   tbr_request req;
   uint64_t ticket;
   int n = 0, k = 0;
-  size_t rec_off = 0, rec_bytes = 0;
+  size_t rec_off = 0, rec_bytes = 0;  // the footprint: records, then arena outputs
+  size_t out_bytes = 0;
+  OutLayout out{};
   int tiles = 0;
   ReqState state = kQueued;
   double t_submit = 0, t_admit = 0, t_start = 0, t_done = 0;
@@ -151,6 +173,7 @@ struct Tick {
   hipGraphNode_t n_copy = nullptr, n_fill = nullptr, n_prep = nullptr, n_serve = nullptr;
   std::vector<uint64_t> tickets;
   double fake_done = 0;  // fake executor: modelled completion time
+  bool fake_fail = false;  // fake executor: this launch reports a device error
 };
 
 }  // namespace
@@ -170,6 +193,8 @@ struct tbr_server {
   std::vector<uint64_t> ready;   // admitted, not launched
   std::vector<Tick> ticks;
   int admitted = 0;              // admitted or running
+  size_t fixed = 0;              // arena bytes held for good: launch buffers, programs
+  int64_t launch_count = 0;
   tbr_serve_stats stats{};
   std::string error;             // first device error (fatal for the server)
 };
@@ -234,26 +259,33 @@ void retire(tbr_server* s) {
   const double t = now_s();
   for (auto& tk : s->ticks) {
     if (!tk.busy) continue;
-    bool finished;
+    bool failed = false;
     if (s->opts.fake_device) {
-      finished = t >= tk.fake_done;
+      if (t < tk.fake_done) continue;
+      failed = tk.fake_fail;
+      if (failed && s->error.empty()) s->error = "device error (fake executor)";
     } else {
       hipError_t e = hipEventQuery(tk.done);
       if (e == hipErrorNotReady) continue;
-      if (e != hipSuccess && s->error.empty()) s->error = hipGetErrorString(e);
-      finished = true;
+      if (e != hipSuccess) {
+        failed = true;
+        if (s->error.empty()) s->error = hipGetErrorString(e);
+      }
     }
-    if (!finished) continue;
     for (uint64_t id : tk.tickets) {
       auto it = s->requests.find(id);
       if (it == s->requests.end()) continue;
       Request& r = it->second;
-      r.state = kDone;
+      r.state = failed ? kFailed : kDone;
       r.t_done = t;
+      // the records are free once the launch is over; arena outputs stay
+      // until tbr_serve_release (or, for a failed request, its poll)
       s->arena.release(r.rec_off, r.rec_bytes);
       --s->admitted;
-      ++s->stats.completed;
-      s->stats.pixel_strokes += (int64_t)r.req.width * r.req.height * r.n;
+      if (!failed) {
+        ++s->stats.completed;
+        s->stats.pixel_strokes += (int64_t)r.req.width * r.req.height * r.n;
+      }
     }
     tk.tickets.clear();
     tk.busy = false;
@@ -266,7 +298,7 @@ void admit(tbr_server* s) {
     uint64_t id = s->queue.front();
     Request& r = s->requests[id];
     size_t off;
-    if (!s->arena.alloc(r.rec_bytes, &off)) break;  // wait for memory (FIFO)
+    if (!s->arena.alloc(r.rec_bytes + r.out_bytes, &off)) break;  // wait for memory (FIFO)
     r.rec_off = off;
     r.state = kAdmitted;
     r.t_admit = t;
@@ -303,7 +335,9 @@ tbr_status launch(tbr_server* s) {
   tk->busy = true;
   tk->tickets = take;
   ++s->stats.launches;
+  ++s->launch_count;
   if (s->opts.fake_device) {
+    tk->fake_fail = s->opts.fake_fail_launch > 0 && s->launch_count == s->opts.fake_fail_launch;
     double cost = 0;
     for (uint64_t id : take) {
       Request& r = s->requests[id];
@@ -341,9 +375,11 @@ tbr_status launch(tbr_server* s) {
     ServeDesc d{};
     d.recs = recs;
     d.palette = kp.palette;
-    d.rgb = r.req.rgb;
-    d.label = r.req.label;
-    d.owner = r.req.owner;
+    char* outs = s->base + r.rec_off + r.rec_bytes;
+    const int32_t m = r.req.arena_outputs;
+    d.rgb = (m & TBR_OUT_RGB) ? reinterpret_cast<float*>(outs + r.out.rgb) : r.req.rgb;
+    d.label = (m & TBR_OUT_LABEL) ? reinterpret_cast<int32_t*>(outs + r.out.label) : r.req.label;
+    d.owner = (m & TBR_OUT_OWNER) ? reinterpret_cast<int32_t*>(outs + r.out.owner) : r.req.owner;
     d.n = n;
     d.width = r.req.width;
     d.height = r.req.height;
@@ -455,6 +491,11 @@ size_t tbr_serve_request_bytes(int32_t n_strokes) {
   return record_bytes(n_strokes);
 }
 
+size_t tbr_serve_output_bytes(int32_t width, int32_t height, int32_t arena_outputs) {
+  if (width < 1 || height < 1 || (arena_outputs & ~TBR_OUT_ALL)) return 0;
+  return out_layout(width, height, arena_outputs).total;
+}
+
 tbr_status tbr_serve_create(const tbr_serve_opts* opts, tbr_server** out) {
   tbr_status st;
   if ((st = check_serve_opts(opts))) return st;
@@ -472,6 +513,7 @@ tbr_status tbr_serve_create(const tbr_serve_opts* opts, tbr_server** out) {
       return sfail(TBR_E_NOMEM, "arena too small for %d launch buffers", opts->streams);
     }
     tk.off = off;
+    s->fixed += align_up(TL.total);
     if (!opts->fake_device) {
       hipError_t e = hipStreamCreateWithFlags(&tk.stream, hipStreamNonBlocking);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&tk.done, hipEventDisableTiming);
@@ -524,6 +566,7 @@ tbr_status tbr_serve_register_program(tbr_server* s, const tbr_program* p, uint6
   }
   *program_id = s->next_program++;
   s->programs[*program_id] = pg;
+  s->fixed += align_up(pg.bytes);
   return TBR_OK;
 }
 
@@ -535,9 +578,18 @@ tbr_status tbr_serve_submit(tbr_server* s, const tbr_request* req, uint64_t* tic
     return sfail(TBR_E_INVALID, "canvas %dx%d outside 1..16384", req->width, req->height);
   if (!(req->tau >= 0.f) || !(req->tau_c >= 0.f) || !(req->eps_floor > 0.f))
     return sfail(TBR_E_INVALID, "tau, tau_c must be >= 0 and eps_floor > 0");
+  const int32_t m = req->arena_outputs;
+  if (m & ~TBR_OUT_ALL) return sfail(TBR_E_INVALID, "arena_outputs %d is not a TBR_OUT_* mask", m);
+  if (req->mode == TBR_SOFT && (m & (TBR_OUT_LABEL | TBR_OUT_OWNER)))
+    return sfail(TBR_E_INVALID, "a soft request has only an rgb output");
+  if (((m & TBR_OUT_RGB) && req->rgb) || ((m & TBR_OUT_LABEL) && req->label) ||
+      ((m & TBR_OUT_OWNER) && req->owner))
+    return sfail(TBR_E_INVALID, "an output held in the arena must have a NULL pointer");
   if (!s->opts.fake_device) {
-    if (req->mode == TBR_SOFT && !req->rgb) return sfail(TBR_E_INVALID, "soft request without rgb");
-    if (req->mode == TBR_HARD && !req->rgb && !req->label && !req->owner)
+    const bool rgb = req->rgb || (m & TBR_OUT_RGB);
+    if (req->mode == TBR_SOFT && !rgb) return sfail(TBR_E_INVALID, "soft request without rgb");
+    if (req->mode == TBR_HARD && !rgb && !req->label && !req->owner && !(m & TBR_OUT_LABEL) &&
+        !(m & TBR_OUT_OWNER))
       return sfail(TBR_E_INVALID, "hard request without any output");
   }
   std::unique_lock<std::mutex> lk(s->mu);
@@ -549,11 +601,16 @@ tbr_status tbr_serve_submit(tbr_server* s, const tbr_request* req, uint64_t* tic
   r.n = pit->second.n;
   r.k = pit->second.k;
   r.rec_bytes = record_bytes(r.n);
+  r.out = out_layout(req->width, req->height, m);
+  r.out_bytes = r.out.total;
   r.tiles = tiles_of(*req);
   if (r.tiles > s->opts.max_tick_items)
     return sfail(TBR_E_NOMEM, "request has %d tiles > max_tick_items %d", r.tiles,
                  s->opts.max_tick_items);
-  if (align_up(r.rec_bytes) > s->arena.size()) return sfail(TBR_E_NOMEM, "request exceeds arena");
+  if (r.rec_bytes + r.out_bytes > s->arena.size() - s->fixed)
+    return sfail(TBR_E_NOMEM, "request footprint %zu bytes exceeds the arena's %zu free of "
+                 "launch buffers and programs", r.rec_bytes + r.out_bytes,
+                 s->arena.size() - s->fixed);
   if ((int)s->queue.size() >= s->opts.max_queue) return sfail(TBR_E_CAPACITY, "queue full");
   r.ticket = s->next_ticket++;
   r.t_submit = now_s();
@@ -577,10 +634,30 @@ tbr_status tbr_serve_poll(tbr_server* s, uint64_t ticket, tbr_result* out) {
   out->t_start = r.t_start;
   out->t_done = r.t_done;
   out->pixel_strokes = (int64_t)r.req.width * r.req.height * r.n;
+  out->rgb = r.req.rgb;
+  out->label = r.req.label;
+  out->owner = r.req.owner;
   if (r.state == kDone) {
     out->status = TBR_OK;
-    s->requests.erase(it);
+    if (r.out_bytes == 0) {
+      s->requests.erase(it);
+      return TBR_OK;
+    }
+    // outputs held in the arena: their addresses, until tbr_serve_release
+    const int32_t m = r.req.arena_outputs;
+    char* outs = s->opts.fake_device ? nullptr : s->base + r.rec_off + r.rec_bytes;
+    if (outs) {
+      if (m & TBR_OUT_RGB) out->rgb = reinterpret_cast<float*>(outs + r.out.rgb);
+      if (m & TBR_OUT_LABEL) out->label = reinterpret_cast<int32_t*>(outs + r.out.label);
+      if (m & TBR_OUT_OWNER) out->owner = reinterpret_cast<int32_t*>(outs + r.out.owner);
+    }
     return TBR_OK;
+  }
+  if (r.state == kFailed) {
+    out->status = TBR_E_DEVICE;
+    if (r.out_bytes) s->arena.release(r.rec_off + r.rec_bytes, r.out_bytes);
+    s->requests.erase(it);
+    return sfail(TBR_E_DEVICE, "request failed on the device: %s", s->error.c_str());
   }
   if (r.state == kCancelled) {
     out->status = TBR_E_CANCELLED;
@@ -593,6 +670,24 @@ tbr_status tbr_serve_poll(tbr_server* s, uint64_t ticket, tbr_result* out) {
   }
   out->status = TBR_PENDING;
   return TBR_PENDING;
+}
+
+tbr_status tbr_serve_release(tbr_server* s, uint64_t ticket) {
+  if (!s) return sfail(TBR_E_INVALID, "null argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->requests.find(ticket);
+  if (it == s->requests.end()) return sfail(TBR_E_NOTFOUND, "unknown ticket");
+  Request& r = it->second;
+  if (r.state != kDone) {
+    if (r.state == kFailed || r.state == kCancelled)
+      return sfail(TBR_E_INVALID, "the ticket ended without outputs: poll it");
+    return TBR_PENDING;
+  }
+  if (r.out_bytes) s->arena.release(r.rec_off + r.rec_bytes, r.out_bytes);
+  s->requests.erase(it);
+  lk.unlock();
+  s->cv.notify_one();  // the freed bytes may admit a waiting request
+  return TBR_OK;
 }
 
 tbr_status tbr_serve_cancel(tbr_server* s, uint64_t ticket) {

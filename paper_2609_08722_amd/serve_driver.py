@@ -8,6 +8,7 @@ spends waiting (for the server or for the plain loop) counts.
 
 from __future__ import annotations
 
+import ctypes as C
 import sys
 import time
 
@@ -18,9 +19,9 @@ from . import api, synth
 
 
 class Pool:
-    """Device-resident request inputs: seeded programs and output buffers."""
+    """Device-resident request inputs: the seeded programs of the mix."""
 
-    def __init__(self, mix: synth.ServeMix, n_buffers: int = 48, device="cuda"):
+    def __init__(self, mix: synth.ServeMix, device="cuda"):
         self.mix = mix
         lens = mix.program_lengths()
         self.programs = [api.to_device(synth.make_program(int(lens[j]), 8,
@@ -28,12 +29,6 @@ class Pool:
                                        device=device)
                          for j in range(mix.n_programs)]
         self.lengths = lens
-        self.free = {}
-        self.bufs = {}
-        for res in mix.resolutions:
-            self.bufs[res] = [torch.empty((res, res, 3), dtype=torch.float32, device=device)
-                              for _ in range(n_buffers)]
-            self.free[res] = list(range(n_buffers))
 
 
 def _percentiles(lat):
@@ -43,28 +38,32 @@ def _percentiles(lat):
     return float(np.percentile(a, 50)), float(np.percentile(a, 99))
 
 
-def run_server(pool: Pool, trace, warmup: float, streams=3, max_slots=64):
-    """Serve the trace; returns latency / throughput statistics."""
-    arena = sum(api.L.load().tbr_serve_program_bytes(len(p["cx"]), 8) for p in pool.programs)
-    srv = api.Server(arena_bytes=arena + (96 << 20), max_slots=max_slots, max_queue=1 << 16,
-                     max_tick_items=1 << 17, streams=streams)
+def run_server(pool: Pool, trace, warmup: float, streams=3, max_slots=64,
+               output_bytes: int = 1 << 30):
+    """Serve the trace; returns latency / throughput statistics. The server
+    holds every request's rgb output in its arena, so it admits requests by
+    their whole footprint (stroke records and output) within output_bytes
+    of room beside the programs and launch buffers; each output is given
+    back as soon as its request completes."""
+    lib = api.L.load()
+    progs = sum(lib.tbr_serve_program_bytes(len(p["cx"]), 8) for p in pool.programs)
+    probe = api.L.ServeOpts(None, 0, max_slots, 1 << 16, 1 << 17, streams, 0, 0.0, 0)
+    ticks = streams * lib.tbr_serve_tick_bytes(C.byref(probe))
+    srv = api.Server(arena_bytes=progs + ticks + output_bytes, max_slots=max_slots,
+                     max_queue=1 << 16, max_tick_items=1 << 17, streams=streams)
     pids = [srv.register(p) for p in pool.programs]
     torch.cuda.synchronize()
     t0 = srv.now() + 0.05
-    pending = {}       # ticket -> (request index, resolution, buffer)
-    waiting = list(range(len(trace)))
+    pending = {}       # ticket -> request index
     lat, ps, t_last, done = [], 0, t0, 0
     j = 0
-    while j < len(waiting) or pending:
+    while j < len(trace) or pending:
         now = srv.now()
-        while j < len(waiting) and trace[waiting[j]].t_arrival + t0 <= now:
-            rq = trace[waiting[j]]
-            if not pool.free[rq.width]:
-                break  # all output buffers of this size are busy: the request waits
-            b = pool.free[rq.width].pop()
+        while j < len(trace) and trace[j].t_arrival + t0 <= now:
+            rq = trace[j]
             t = srv.submit(pids[rq.program], "soft" if rq.soft else "hard", rq.width, rq.width,
-                           rgb=pool.bufs[rq.width][b], tau_c=0.0)
-            pending[t] = (waiting[j], rq.width, b)
+                           tau_c=0.0, arena_outputs=("rgb",))
+            pending[t] = j
             j += 1
         progressed = False
         for t in list(pending):
@@ -72,8 +71,8 @@ def run_server(pool: Pool, trace, warmup: float, streams=3, max_slots=64):
             if r is None:
                 continue
             progressed = True
-            idx, res, b = pending.pop(t)
-            pool.free[res].append(b)
+            srv.release(t)  # the output is not read here
+            idx = pending.pop(t)
             rq = trace[idx]
             if rq.t_arrival >= warmup:
                 lat.append(r["t_done"] - (rq.t_arrival + t0))

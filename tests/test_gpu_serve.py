@@ -1,7 +1,11 @@
 """GPU checks of the continuous-batching server: every request's result is
 bitwise the same whether it runs alone (tbr_render) or packed with others of
-different programs, modes and resolutions; a short Poisson replay completes
-every request."""
+different programs, modes and resolutions; a request waits for arena room
+for its whole footprint (records and server-held outputs); a short Poisson
+replay completes every request."""
+
+import ctypes as C
+import time
 
 import numpy as np
 import pytest
@@ -55,7 +59,7 @@ def test_short_poisson_replay_completes():
     require_gpu()
     mix = synth.ServeMix(rate=200.0, n_programs=16)
     trace = mix.trace(1.5)
-    pool = serve_driver.Pool(mix, n_buffers=24)
+    pool = serve_driver.Pool(mix)
     r = serve_driver.run_server(pool, trace, warmup=0.0)
     log(f"[serve] {r}")
     assert r["requests"] == len(trace)
@@ -147,3 +151,56 @@ def test_tick_graph_replays_match_eager_renders():
     srv.close()
     log(f"[serve] graph replays: {stats['launches']} ticks on one stream")
     assert stats["launches"] >= 6
+
+
+def test_request_waits_for_arena_room_then_matches_render():
+    """The arena holds one 2048^2 request's footprint (stroke records and
+    the server-held rgb, label and owner) and not two: the second request
+    waits until the first one's outputs are released, then both results
+    equal tbr_render bitwise."""
+    require_gpu()
+    lib = api.L.load()
+    mix = synth.ServeMix()
+    lens = mix.program_lengths()
+    j = int(np.argmax(lens))
+    prog = synth.make_program(int(lens[j]), 8, mix.program_seed0 + j)
+    dp = api.to_device(prog)
+    W, n = 2048, int(lens[j])
+    names = ("rgb", "label", "owner")
+    foot = lib.tbr_serve_request_bytes(n) + lib.tbr_serve_output_bytes(W, W, api.L.TBR_OUT_ALL)
+    opts = api.L.ServeOpts(None, 0, 8, 1 << 16, 1 << 15, 2, 0, 0.0, 0)
+    tick = lib.tbr_serve_tick_bytes(C.byref(opts))
+    arena = 2 * tick + lib.tbr_serve_program_bytes(n, 8) + foot + foot // 2
+    srv = api.Server(arena_bytes=arena, max_slots=8, max_queue=1 << 16, max_tick_items=1 << 15,
+                     streams=2)
+    pid = srv.register(dp)
+    a = srv.submit(pid, "hard", W, W, tau_c=0.0, arena_outputs=names)
+    b = srv.submit(pid, "hard", W, W, tau_c=0.0, arena_outputs=names)
+    ra = None
+    while ra is None:
+        ra = srv.poll(a)
+    torch.cuda.synchronize()
+    got_a = {k: ra[k].clone() for k in names}
+    torch.cuda.synchronize()
+    time.sleep(0.05)
+    st = srv.stats()
+    waited = st["queued"] == 1 and srv.poll(b) is None
+    assert srv.release(a) == api.L.TBR_OK
+    rb = None
+    while rb is None:
+        rb = srv.poll(b)
+    torch.cuda.synchronize()
+    got_b = {k: rb[k].clone() for k in names}
+    torch.cuda.synchronize()
+    assert srv.release(b) == api.L.TBR_OK
+    stats = srv.stats()
+    srv.close()
+    log(f"[serve arena room] footprint {foot / 2**20:.1f} MiB, arena {arena / 2**20:.1f} MiB; "
+        f"second request waited: {waited}; admitted {rb['t_admit'] - ra['t_done']:.4f} s "
+        f"after the first finished")
+    assert waited and rb["t_admit"] >= ra["t_done"]
+    assert stats["arena_used"] == 2 * tick + lib.tbr_serve_program_bytes(n, 8)
+    alone = api.render(dp, api.Opts(W, W, tau_c=0.0), "hard")
+    for got in (got_a, got_b):
+        for k in names:
+            assert torch.equal(alone[k], got[k]), k

@@ -1,6 +1,8 @@
 """Host-only checks of the serving scheduler (fake executor: no GPU work):
-FIFO admission by slots and arena bytes, queue capacity, cancellation, and
-that every request completes exactly once."""
+FIFO admission by slots and by the arena bytes of a request's whole
+footprint (stroke records and server-held outputs), queue capacity,
+cancellation, a launch that fails on the device, and that every request
+completes exactly once."""
 
 import ctypes as C
 import time
@@ -47,7 +49,7 @@ def test_admission_limited_by_arena_bytes():
     n = 4000
     rec = L.load().tbr_serve_request_bytes(n)
     prog_bytes = L.load().tbr_serve_program_bytes(n, 8)
-    probe = L.ServeOpts(None, 0, 16, 4096, 8192, 1, 1, 0.0)
+    probe = L.ServeOpts(None, 0, 16, 4096, 8192, 1, 1, 0.0, 0)
     tick = L.load().tbr_serve_tick_bytes(C.byref(probe))
     srv = api.Server(arena_bytes=tick + prog_bytes + 2 * rec + rec // 2, max_slots=16,
                      max_tick_items=8192, streams=1, fake_device=True,
@@ -99,4 +101,73 @@ def test_invalid_requests_rejected():
     with pytest.raises(L.TbrError) as e:  # more tiles than one launch can hold
         srv.submit(pid, "soft", 16384, 16384)
     assert e.value.status == L.TBR_E_NOMEM
+    srv.close()
+
+
+def test_admission_counts_held_outputs_until_release():
+    """A request's footprint includes the outputs the server holds for it:
+    with room for one 2048^2 request's rgb, the second waits until the first
+    is released, not merely until its launch ends."""
+    lib = L.load()
+    n, W = 300, 2048
+    rec = lib.tbr_serve_request_bytes(n)
+    out = lib.tbr_serve_output_bytes(W, W, L.TBR_OUT_RGB)
+    assert out == W * W * 12
+    assert lib.tbr_serve_output_bytes(W, W, L.TBR_OUT_ALL) == W * W * 20
+    prog_bytes = lib.tbr_serve_program_bytes(n, 8)
+    probe = L.ServeOpts(None, 0, 8, 4096, 1 << 15, 1, 1, 0.0, 0)
+    tick = lib.tbr_serve_tick_bytes(C.byref(probe))
+    srv = api.Server(arena_bytes=tick + prog_bytes + rec + out + out // 2, max_slots=8,
+                     max_tick_items=1 << 15, streams=1, fake_device=True,
+                     fake_ns_per_pixel_stroke=1e-4)
+    pid = srv.register(synth.make_program(n, 8, 5))
+    a = srv.submit(pid, "soft", W, W, arena_outputs=("rgb",))
+    b = srv.submit(pid, "soft", W, W, arena_outputs=("rgb",))
+    ra = wait_all(srv, [a])[a]
+    assert ra["status"] == L.TBR_OK
+    time.sleep(0.05)
+    st = srv.stats()
+    assert st["queued"] == 1 and st["in_flight"] == 0  # b waits for a's held rgb
+    assert srv.poll(b) is None
+    assert srv.release(a) == L.TBR_OK
+    rb = wait_all(srv, [b])[b]
+    assert rb["status"] == L.TBR_OK and rb["t_admit"] >= ra["t_done"]
+    assert srv.stats()["arena_used"] == tick + prog_bytes + out  # b's rgb is still held
+    assert srv.release(b) == L.TBR_OK
+    assert srv.stats()["arena_used"] == tick + prog_bytes
+    with pytest.raises(L.TbrError) as e:  # a footprint larger than the arena's room
+        srv.submit(pid, "hard", W, W, arena_outputs=("rgb", "label", "owner"))
+    assert e.value.status == L.TBR_E_NOMEM
+    for bad in (dict(arena_outputs=("label",)),):  # a soft request has only rgb
+        with pytest.raises(L.TbrError) as e:
+            srv.submit(pid, "soft", 64, 64, **bad)
+        assert e.value.status == L.TBR_E_INVALID
+    srv.close()
+
+
+def test_failed_launch_reports_a_device_error():
+    """Requests of a launch that fails report TBR_E_DEVICE, never TBR_OK,
+    and the server accepts no further work."""
+    srv = api.Server(arena_bytes=64 << 20, max_slots=2, streams=1, fake_device=True,
+                     fake_ns_per_pixel_stroke=1e-3, fake_fail_launch=1)
+    pid = srv.register(synth.make_program(200, 8, 6))
+    tickets = [srv.submit(pid, "soft", 128, 128) for _ in range(2)]
+    t0 = time.time()
+    statuses = {}
+    while len(statuses) < 2 and time.time() - t0 < 10:
+        for t in tickets:
+            if t in statuses:
+                continue
+            try:
+                r = srv.poll(t)
+                if r is not None:
+                    statuses[t] = r["status"]
+            except L.TbrError as e:
+                statuses[t] = e.status
+        time.sleep(0.001)
+    assert set(statuses.values()) == {L.TBR_E_DEVICE}
+    with pytest.raises(L.TbrError) as e:
+        srv.submit(pid, "soft", 64, 64)
+    assert e.value.status == L.TBR_E_DEVICE
+    assert srv.stats()["completed"] == 0
     srv.close()
