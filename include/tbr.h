@@ -361,8 +361,10 @@ void tbr_schedule_at(int32_t step, int32_t total_steps, float tau_first, float t
  *      arena can hold the request's HBM footprint: its prepared stroke
  *      records (tbr_serve_request_bytes) plus the outputs it asks the server
  *      to hold in the arena (tbr_serve_output_bytes);
- *   3. packs all admitted requests into one persistent launch over
- *      (request, 16x16 tile) work items.
+ *   3. packs the admitted requests into one persistent launch over
+ *      (request, 16x16 tile) work items; the requests of a launch retire
+ *      together, so one of at least solo_tiles tiles gets a launch of its
+ *      own.
  * Each stream owns a hipGraph built at create time: one copy of the tick's
  * descriptors and work list from pinned host staging, a kernel that clears
  * the work cursor, one stroke-preparation launch for all of the tick's
@@ -390,6 +392,8 @@ typedef struct tbr_serve_opts {
   float fake_ns_per_pixel_stroke; /* fake executor: modelled cost per pixel-stroke */
   int32_t fake_fail_launch;       /* fake executor: the 1-based launch that reports a device
                                      error on completion (0: none); ignored on a GPU */
+  int32_t solo_tiles;             /* a request of at least this many 16x16 tiles runs in a
+                                     launch of its own (0: every request may share one) */
 } tbr_serve_opts;
 
 /* Outputs of a request that the server holds in its arena. */

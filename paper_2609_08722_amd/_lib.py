@@ -73,7 +73,7 @@ class ServeOpts(C.Structure):
     _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("max_slots", C.c_int32),
                 ("max_queue", C.c_int32), ("max_tick_items", C.c_int32), ("streams", C.c_int32),
                 ("fake_device", C.c_int32), ("fake_ns_per_pixel_stroke", C.c_float),
-                ("fake_fail_launch", C.c_int32)]
+                ("fake_fail_launch", C.c_int32), ("solo_tiles", C.c_int32)]
 
 
 class Request(C.Structure):

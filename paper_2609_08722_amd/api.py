@@ -425,14 +425,14 @@ class Server:
     def __init__(self, arena_bytes: int = 256 << 20, max_slots: int = 64, max_queue: int = 4096,
                  max_tick_items: int = 1 << 17, streams: int = 3, fake_device: bool = False,
                  fake_ns_per_pixel_stroke: float = 0.0, fake_fail_launch: int = 0,
-                 device="cuda"):
+                 solo_tiles: int = 1024, device="cuda"):
         lib = L.load()
         self.arena = None if fake_device else torch.empty(arena_bytes, dtype=torch.uint8,
                                                           device=device)
         self.opts = L.ServeOpts(_ptr(self.arena), int(arena_bytes), int(max_slots),
                                 int(max_queue), int(max_tick_items), int(streams),
                                 int(fake_device), float(fake_ns_per_pixel_stroke),
-                                int(fake_fail_launch))
+                                int(fake_fail_launch), int(solo_tiles))
         h = C.c_void_p()
         L.check(lib.tbr_serve_create(C.byref(self.opts), C.byref(h)))
         self.h = h

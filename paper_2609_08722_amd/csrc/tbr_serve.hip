@@ -321,13 +321,20 @@ tbr_status launch(tbr_server* s) {
   std::vector<uint64_t> take;
   int n_items = 0;
   size_t used = 0;
+  // A request of at least solo_tiles tiles runs in a launch of its own:
+  // requests of one launch retire together, so a large request packed with
+  // small ones would hold them back, or be held back by them.
+  const int solo = s->opts.solo_tiles;
   for (uint64_t id : s->ready) {
     Request& r = s->requests[id];
     if (take.size() >= (size_t)s->opts.max_slots) break;
     if (n_items + r.tiles > s->opts.max_tick_items) break;
+    const bool big = solo > 0 && r.tiles >= solo;
+    if (big && !take.empty()) break;
     take.push_back(id);
     n_items += r.tiles;
     ++used;
+    if (big) break;
   }
   if (take.empty()) return TBR_OK;
   s->ready.erase(s->ready.begin(), s->ready.begin() + used);

@@ -171,3 +171,23 @@ def test_failed_launch_reports_a_device_error():
     assert e.value.status == L.TBR_E_DEVICE
     assert srv.stats()["completed"] == 0
     srv.close()
+
+
+def test_large_request_gets_a_launch_of_its_own():
+    """Requests of one launch retire together, so a request of at least
+    solo_tiles tiles is launched alone: small requests queued before it go
+    in one launch, it in the next, and those after it in a third."""
+    srv = api.Server(arena_bytes=64 << 20, max_slots=8, streams=1, fake_device=True,
+                     fake_ns_per_pixel_stroke=5e-4, solo_tiles=1024)
+    pid = srv.register(synth.make_program(100, 8, 7))
+    first = srv.submit(pid, "soft", 1024, 1024)  # 4096 tiles: keeps the one stream busy
+    time.sleep(0.01)
+    small = [srv.submit(pid, "soft", 128, 128) for _ in range(2)]
+    big = srv.submit(pid, "hard", 512, 512)      # 1024 tiles
+    after = srv.submit(pid, "soft", 64, 64)
+    done = wait_all(srv, [first, *small, big, after])
+    starts = {t: done[t]["t_start"] for t in done}
+    assert starts[small[0]] == starts[small[1]]
+    assert starts[first] < starts[small[0]] < starts[big] < starts[after]
+    assert srv.stats()["launches"] == 4
+    srv.close()
