@@ -112,8 +112,9 @@ typedef struct tbr_program_grad {
  *     displacement is K = 16 drop maps (Lu 2012) of radius s, K pi s^2 =
  *     A_l(r), at the centres of 16 equal pieces of the segment, laid from its
  *     -e end (e = (cos angle, sin angle)) and undone last to first, each
- *     with the floor pi rho'^2 >= (eps s)^2. Soft and hard renders without a
- *     tape only: a tape, the adjoint and the fit steps return TBR_E_INVALID. */
+ *     with the floor pi rho'^2 >= (eps s)^2. Renders, adjoint and fit steps:
+ *     the tape's side table holds x_i wherever a drop's floor bound, and the
+ *     replay regenerates through the drops' forward maps elsewhere. */
 enum {
   TBR_TRANSPORT_CAPSULE = 0,
   TBR_TRANSPORT_COUPLED = 1,

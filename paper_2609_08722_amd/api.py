@@ -37,7 +37,7 @@ class Opts:
     # calibrated coupling (Eq. coupling, Eq. profile): a contiguous float32
     # CUDA tensor [N, 3] of (c_1, c_2, c_3) per stroke, or None (capsule map)
     coupling: "torch.Tensor | None" = None
-    # "inert" (R_U, psi = id) or "drops16" (R_D, renders only); None: the
+    # "inert" (R_U, psi = id) or "drops16" (R_D, sixteen drops); None: the
     # capsule map, or its coupling when coupling is given
     transport: str | None = None
 

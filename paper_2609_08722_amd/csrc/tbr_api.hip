@@ -172,8 +172,6 @@ tbr_status check_opts(const tbr_render_opts* o, bool soft, bool tape) {
   if (o->side_slots < 0) return fail(TBR_E_INVALID, "side_slots must be >= 0");
   if (o->transport < TBR_TRANSPORT_CAPSULE || o->transport > TBR_TRANSPORT_DROPS16)
     return fail(TBR_E_INVALID, "transport %d is not a TBR_TRANSPORT_* value", o->transport);
-  if (tape && o->transport == TBR_TRANSPORT_DROPS16)
-    return fail(TBR_E_INVALID, "the 16-drop transport renders only: no tape, adjoint or fit");
   if (coupled(o) && !o->coupling)
     return fail(TBR_E_INVALID, "the coupled transport needs the coupling coefficients");
   return TBR_OK;
@@ -260,6 +258,7 @@ tbr_status launch_fused(const FitJobsK& K, int* cursor, int transport, hipStream
     switch (transport) {
       case kCoupled: k_fit_fused<kCoupled><<<grid, 256, 0, st>>>(K, cursor); break;
       case kInert: k_fit_fused<kInert><<<grid, 256, 0, st>>>(K, cursor); break;
+      case kDrops: k_fit_fused<kDrops><<<grid, 256, 0, st>>>(K, cursor); break;
       default: k_fit_fused<kCapsule><<<grid, 256, 0, st>>>(K, cursor); break;
     }
   }
@@ -285,6 +284,10 @@ tbr_status launch_backward(const tbr_program* p, const tbr_render_opts* o, const
         break;
       case kInert:
         k_replay<kInert><<<grid, 256, 0, st>>>(recs, nullptr, n, W, H, p->palette, grad_rgb, t,
+                                               partial);
+        break;
+      case kDrops:
+        k_replay<kDrops><<<grid, 256, 0, st>>>(recs, nullptr, n, W, H, p->palette, grad_rgb, t,
                                                partial);
         break;
       default:

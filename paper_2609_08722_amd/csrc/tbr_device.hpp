@@ -463,13 +463,16 @@ __device__ __forceinline__ Move regenerate(const Chart& c, const StrokeRec& g, c
 // displacements, which are then added to the FP64 state: rho' / rho - 1 =
 // (rho'^2 - rho^2) / (rho^2 (1 + rho' / rho)) has no cancellation.
 constexpr int kNumDrops = 16;
-__device__ __forceinline__ void drops_backward(double& x, double& y, const StrokeRec& g) {
+// Returns whether a drop's floor bound (the replay then takes x_i from the
+// side table: no map inverts a floored drop).
+__device__ __forceinline__ bool drops_backward(double& x, double& y, const StrokeRec& g) {
   const float s2 = g.ar * (1.f / (kNumDrops * kPi));
   // eps^2 = floor_c / r^2, so the floor on rho'^2 is floor_c s^2 / (pi r^2)
   const float fl = g.r > 0.f ? g.floor_c * rcp(g.r * g.r) * (s2 * (1.f / kPi)) : 0.f;
   const float ux = g.ell * g.ce, uy = g.ell * g.se;  // the segment, -e end to +e end
   const float d0x = (float)(x - g.mx), d0y = (float)(y - g.my);
   float Dx = 0.f, Dy = 0.f;
+  bool any = false;
 #pragma unroll
   for (int j = kNumDrops - 1; j >= 0; --j) {
     const float f = ((float)j + 0.5f) * (1.f / kNumDrops) - 0.5f;
@@ -477,6 +480,7 @@ __device__ __forceinline__ void drops_backward(double& x, double& y, const Strok
     const float rho2 = fmaf(px, px, py * py);
     const float cq = rho2 - s2;
     const bool floored = cq < fl;
+    any |= floored;
     const float num = floored ? fl - rho2 : -s2;  // rho'^2 - rho^2
     const float inv = rho2 > 0.f ? rcp(rho2) : 0.f;
     const float k = hw_sqrt((floored ? fl : cq) * inv);
@@ -486,6 +490,120 @@ __device__ __forceinline__ void drops_backward(double& x, double& y, const Strok
   }
   x += (double)Dx;
   y += (double)Dy;
+  return any;
+}
+
+// The adjoint of R_D's displacement in the replay, with the stroke's
+// contributions through the drops (d/d(m_x, m_y, phi, l, r); coverage is
+// the caller's). psi_D = b_0 o b_1 o ... o b_15 (b_j the backward map of drop
+// j, undone last drop first), so lambda^x_i = J_15^T ... J_0^T lambda^x_{i-1}
+// with J_j the Jacobian of b_j at its input: b_0's comes first.
+//  * Regenerated lane (the state holds x_{i-1}): drop 0's forward map is
+//    applied first, p = c + (q - c) sqrt(1 + s^2 / |q - c|^2), so the points
+//    met in that order are exactly the inputs of b_0, b_1, ...; the state
+//    ends at x_i.
+//  * Loaded lane (the state holds x_i, taken where a floor bound): the input
+//    of b_j is recomputed from x_i through b_15 .. b_{j+1}, floors included.
+// b_j(p) = c + v k with v = p - c, rho^2 = |v|^2 and k = sqrt(1 - s^2/rho^2),
+// or k = sqrt(fl / rho^2) where the floor binds; J = k I + (s^2/(k rho^4)) v v^T
+// (floored: k (I - v v^T / rho^2)) is symmetric, and its change
+// (J - I) lambda = (k - 1) lambda + coef (v . lambda) v, with
+// k - 1 = -(s^2/rho^2) / (1 + k), is formed without cancellation. The drop's
+// centre c_j = m + f_j l e receives -(J - I) lambda; s^2 = A_l(r) / (16 pi)
+// receives v . lambda dk/d(s^2).
+struct DropsAdj {
+  float gmx, gmy, gphi, gell, gr;
+};
+
+__device__ __forceinline__ DropsAdj drops_replay(double& x, double& y, const StrokeRec& g,
+                                                 bool loaded, float& lx, float& ly) {
+  const float s2 = g.ar * (1.f / (kNumDrops * kPi));
+  const float fl = g.r > 0.f ? g.floor_c * rcp(g.r * g.r) * (s2 * (1.f / kPi)) : 0.f;
+  const float inv_s2 = s2 > 0.f ? rcp(s2) : 0.f;
+  const float ux = g.ell * g.ce, uy = g.ell * g.se;
+  const float d0x = (float)(x - g.mx), d0y = (float)(y - g.my);
+  float Dx = 0.f, Dy = 0.f;  // regenerated displacement from x_{i-1}
+  float Sx = 0.f, Sy = 0.f;  // sum of (J_j - I) lambda_j
+  float Fx = 0.f, Fy = 0.f;  // sum of f_j (J_j - I) lambda_j
+  float S2 = 0.f;            // adjoint of s^2
+  for (int j = 0; j < kNumDrops; ++j) {
+    const float f = ((float)j + 0.5f) * (1.f / kNumDrops) - 0.5f;
+    float vx, vy, rho2, km1, coef, dk;  // (J - I) lambda = km1 lambda + coef (v.lambda) v; dk/d(s^2)
+    if (loaded) {
+      float Ex = 0.f, Ey = 0.f;
+      for (int jj = kNumDrops - 1; jj > j; --jj) {
+        const float fj = ((float)jj + 0.5f) * (1.f / kNumDrops) - 0.5f;
+        const float px = fmaf(-fj, ux, d0x) + Ex, py = fmaf(-fj, uy, d0y) + Ey;
+        const float r2 = fmaf(px, px, py * py);
+        const float cq = r2 - s2;
+        const bool fb = cq < fl;
+        const float num = fb ? fl - r2 : -s2;
+        const float inv = r2 > 0.f ? rcp(r2) : 0.f;
+        const float k = hw_sqrt((fb ? fl : cq) * inv);
+        const float sc = num * inv * rcp(1.f + k);
+        Ex = fmaf(px, sc, Ex);
+        Ey = fmaf(py, sc, Ey);
+      }
+      vx = fmaf(-f, ux, d0x) + Ex;
+      vy = fmaf(-f, uy, d0y) + Ey;
+      rho2 = fmaf(vx, vx, vy * vy);
+      const float inv = rho2 > 0.f ? rcp(rho2) : 0.f;
+      if (rho2 - s2 < fl) {  // k = sqrt(fl / rho^2), fl proportional to s^2
+        const float k = hw_sqrt(fl * inv);
+        km1 = k - 1.f;
+        coef = -k * inv;
+        dk = 0.5f * k * inv_s2;   // dk/d(s^2) = k / (2 s^2)
+      } else {
+        const float a = s2 * inv;
+        const float k = hw_sqrt(1.f - a);
+        const float inv_k = rcp(k);
+        km1 = -a * rcp(1.f + k);
+        coef = a * inv * inv_k;
+        dk = -0.5f * inv * inv_k;  // dk/d(s^2) = -1 / (2 k rho^2)
+      }
+    } else {
+      const float qx = fmaf(-f, ux, d0x) + Dx, qy = fmaf(-f, uy, d0y) + Dy;
+      const float q2 = fmaf(qx, qx, qy * qy);
+      const float aq = q2 > 0.f ? s2 * rcp(q2) : 0.f;  // s^2 / |q - c|^2
+      const float m = hw_sqrt(1.f + aq);
+      const float mm1 = aq * rcp(1.f + m);              // m - 1
+      Dx = fmaf(qx, mm1, Dx);
+      Dy = fmaf(qy, mm1, Dy);
+      vx = qx * m;
+      vy = qy * m;
+      rho2 = q2 + s2;
+      const float inv = rcp(rho2);
+      const float a = s2 * inv;     // s^2 / rho^2
+      const float k = rcp(m);       // sqrt(1 - s^2 / rho^2)
+      km1 = -a * rcp(1.f + k);
+      coef = a * inv * m;
+      dk = -0.5f * inv * m;         // dk/d(s^2) = -1 / (2 k rho^2)
+    }
+    const float vl = fmaf(vx, lx, vy * ly);
+    const float ddx = fmaf(km1, lx, coef * vl * vx);
+    const float ddy = fmaf(km1, ly, coef * vl * vy);
+    lx += ddx;
+    ly += ddy;
+    Sx += ddx;
+    Sy += ddy;
+    Fx = fmaf(f, ddx, Fx);
+    Fy = fmaf(f, ddy, Fy);
+    S2 = fmaf(vl, dk, S2);
+  }
+  if (!loaded) {
+    x += (double)Dx;
+    y += (double)Dy;
+  }
+  DropsAdj o;
+  o.gmx = -Sx;
+  o.gmy = -Sy;
+  // c_j = m + f_j l e: dc_j/dphi = f_j l n, dc_j/dl = f_j e
+  o.gphi = -g.ell * fmaf(-Fx, g.se, Fy * g.ce);
+  // s^2 = A_l(r) / (16 pi): d/dl = 2 r / (16 pi), d/dr = P_l(r) / (16 pi)
+  const float s2n = S2 * (1.f / (kNumDrops * kPi));
+  o.gell = fmaf(s2n, 2.f * g.r, -fmaf(Fx, g.ce, Fy * g.se));
+  o.gr = s2n * g.per_r;
+  return o;
 }
 
 // Apply a displacement (a, b) along (e, n), unfolded, to the FP64 state.

@@ -194,7 +194,17 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
   auto transport = [&](int i, const Chart& c, const StrokeRec& g, const Leaf& lf, auto floor_tag) {
     constexpr bool kFloor = decltype(floor_tag)::value;
     if constexpr (kT == kDrops) {
-      drops_backward(x, y, g);  // R_D: rendered only, no tape
+      // R_D: the tape records x_i wherever a drop's floor binds (far steps
+      // included: a drop may reach past the capsule's far margin)
+      const double x0 = x, y0 = y;
+      if (drops_backward(x, y, g)) {
+        if (write_tape && nrec < tape.side_slots) {
+          size_t o = (size_t)nrec * P + id.p;
+          tape.side_idx[o] = i;
+          tape.side_xy[o] = make_double2(x0, y0);
+        }
+        ++nrec;
+      }
     } else if constexpr (kT != kInert) {
       Move mv = kFloor ? displace<false, true>(c, g, true, lf) : psi_far(c, g, lf);
       if constexpr (kFloor) {  // record where the floor binds
@@ -612,6 +622,79 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           float v[8] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
           tot = row_sums8(v, lane);
         }
+        if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
+      }
+      __syncthreads();
+      {
+        const int j = threadIdx.x >> 3, vv = threadIdx.x & 7;
+        if (j < cn) {
+          float s = 0.f;
+#pragma unroll
+          for (int q = 0; q < 16; ++q) s += lds[buf][q][j][vv];
+          prow[(size_t)(c0 + j) * 8 + vv] = s;
+        }
+      }
+    }
+    return;
+  }
+  if constexpr (kT == kDrops) {
+    // R_D: per stroke, the drops' adjoint (which regenerates x_i from
+    // x_{i-1}, or starts from x_i where it is loaded), then the capsule
+    // coverage at x_i as in the other transports.
+    for (int c0 = 0; c0 < n; c0 += kChunk) {
+      const int buf = (c0 / kChunk) & 1;
+      const int cn = min(kChunk, n - c0);
+      for (int j = 0; j < cn; ++j) {
+        const int i = c0 + j;
+        const StrokeRec g = load_rec(recs, i);
+        const bool ck = i == next_ck;
+        if (ck) next_ck = next_ck + k + 1 < n ? next_ck + k : 0x7fffffff;
+        const bool pop = top_idx == i;
+        if (pop) {
+          double2 r = tape.side_xy[(size_t)(top - 1) * P + id.p];
+          x = r.x;
+          y = r.y;
+          --top;
+          top_idx = top > 0 ? tape.side_idx[(size_t)(top - 1) * P + id.p] : -1;
+        }
+        if (ck && id.active) {
+          const double2 r = tape.ckpt_xy[(size_t)((i + 1) / k) * P + id.p];
+          const float2 ckt = tape.ckpt_t[(size_t)((i + 1) / k) * P + id.p];
+          x = r.x;
+          y = r.y;
+          tm = ckt.x;
+          te = (int)ckt.y;
+        }
+        const DropsAdj da = drops_replay(x, y, g, pop || ck, lx, ly);
+        float v[8] = {da.gmx, da.gmy, da.gphi, da.gell, da.gr, 0.f, 0.f, 0.f};
+        Chart ca;
+        chart_dist(x, y, g, ca);
+        if (!wave_all(is_far<false>(ca.sig, uniform_leaf(g), g))) {
+          chart_angle(g, ca);
+          Cover cv = cover(ca.sig, g, g.r);
+          if (!ck) {
+            tm *= cv.inv_q;
+            renorm(tm, te);
+          }
+          const float t = trans_value(tm, te);
+          const float lc = fmaf(lcr, g.cr, fmaf(lcg, g.cg, lcb * g.cb));
+          const float dlt = lc - lt;
+          const float mu = t * dlt;
+          const float ta = t * cv.alpha;
+          lt = fmaf(cv.alpha, dlt, lt);  // (1 - alpha) lt + alpha lc
+          const VjpOut vo = vjp_cover_only(ca, g, cv, mu);
+          lx -= vo.gmx;  // + mu d alpha / dx at x_i
+          ly -= vo.gmy;
+          v[0] += vo.gmx;
+          v[1] += vo.gmy;
+          v[2] += vo.gphi;
+          v[3] += vo.gell;
+          v[4] += vo.gr;
+          v[5] = lcr * ta;
+          v[6] = lcg * ta;
+          v[7] = lcb * ta;
+        }
+        const float tot = row_sums8(v, lane);
         if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
       }
       __syncthreads();
@@ -1287,7 +1370,7 @@ __global__ void __launch_bounds__(kCompThreadsK)
 
 namespace tbr {
 // The per-pixel kernels for each transport: the capsule map, its calibrated
-// coupling, the inert-mark model and (rendering only) the sixteen drops.
+// coupling, the inert-mark model and the sixteen drops.
 #define TBR_INSTANTIATE_RENDER(T)                                                               \
   template __global__ void k_trace_soft<T>(const StrokeRec*, const float4*, int, int, int,      \
                                            const float*, float*, KTape, KSeed);                 \
@@ -1304,6 +1387,7 @@ TBR_INSTANTIATE_RENDER(kDrops)
 TBR_INSTANTIATE_ADJOINT(kCapsule)
 TBR_INSTANTIATE_ADJOINT(kCoupled)
 TBR_INSTANTIATE_ADJOINT(kInert)
+TBR_INSTANTIATE_ADJOINT(kDrops)
 #undef TBR_INSTANTIATE_RENDER
 #undef TBR_INSTANTIATE_ADJOINT
 }  // namespace tbr

@@ -101,7 +101,7 @@ __global__ void k_window_adam(float* th, const float* g_nat, float* m, float* v,
 // Transport variants of the per-pixel kernels (the values of
 // tbr_render_opts.transport): the capsule map, its calibrated coupling (coup
 // = per-stroke profile cubics), the inert-mark model (no displacement), and
-// the sixteen drops of R_D (soft and hard renders only).
+// the sixteen drops of R_D.
 constexpr int kCapsule = 0, kCoupled = 1, kInert = 2, kDrops = 3;
 
 template <int kT>

@@ -206,16 +206,6 @@ def test_coupled_options_need_coefficients(lib):
     assert st == L.TBR_E_INVALID and b"transport" in lib.tbr_last_error()
 
 
-def test_drops_transport_has_no_tape(lib):
-    """R_D renders only: a tape is refused on the host, before any launch."""
-    o = opts(transport=L.TBR_TRANSPORT_DROPS16)
-    prog = L.Program(0, 1, None, None, None, None, None, None, C.c_void_p(16))
-    buf = C.create_string_buffer(1 << 20)
-    st = lib.tbr_render(C.byref(prog), C.byref(o), L.TBR_SOFT, None, None, None,
-                        C.cast(buf, C.c_void_p), 1 << 20, 1, None)
-    assert st == L.TBR_E_INVALID and b"16-drop" in lib.tbr_last_error()
-
-
 def test_compensate_validation(lib):
     """Host-side checks of tbr_compensate (nothing is launched)."""
     buf = C.create_string_buffer(64)

@@ -23,13 +23,15 @@ def close(a, b, rtol, group, atol=0.0):
     return np.abs(a - b) <= rtol * (np.abs(b) + 0.01 * rms) + atol
 
 
-# The last case has a floor width so small that far pixels reach
+# The fourth case has a floor width so small that far pixels reach
 # (r - sigma) / w_d < -709, where exp(-z) overflows in FP64: the coverage
-# and its derivative must still come out as the limits 0, not NaN.
+# and its derivative must still come out as the limits 0, not NaN. The last
+# is the sixteen-drop renderer R_D.
 @pytest.mark.parametrize("tau,tau_c,transport,tau_min", [(1e-3, 1.0, True, None),
                                                           (0.35, 0.5, True, None),
                                                           (1e-3, 1.0, False, None),
-                                                          (1e-3, 1.0, True, 1e-4)])
+                                                          (1e-3, 1.0, True, 1e-4),
+                                                          (1e-3, 1.0, 2, None)])
 def test_gradient_matches_central_differences(orc, tau, tau_c, transport, tau_min):
     W = H = 24
     prog = synth.make_program(12, 4, 21, synth.DIST_SMALL, beta=2.0, dtype=np.float64)

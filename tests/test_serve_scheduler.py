@@ -53,7 +53,7 @@ def test_admission_limited_by_arena_bytes():
     tick = L.load().tbr_serve_tick_bytes(C.byref(probe))
     srv = api.Server(arena_bytes=tick + prog_bytes + 2 * rec + rec // 2, max_slots=16,
                      max_tick_items=8192, streams=1, fake_device=True,
-                     fake_ns_per_pixel_stroke=1e-3)
+                     fake_ns_per_pixel_stroke=0.1)  # 6.6 ms per request
     pid = srv.register(synth.make_program(n, 8, 1))
     tickets = [srv.submit(pid, "soft", 128, 128) for _ in range(12)]
     peak = 0
@@ -178,9 +178,9 @@ def test_large_request_gets_a_launch_of_its_own():
     solo_tiles tiles is launched alone: small requests queued before it go
     in one launch, it in the next, and those after it in a third."""
     srv = api.Server(arena_bytes=64 << 20, max_slots=8, streams=1, fake_device=True,
-                     fake_ns_per_pixel_stroke=5e-4, solo_tiles=1024)
+                     fake_ns_per_pixel_stroke=5.0, solo_tiles=1024)
     pid = srv.register(synth.make_program(100, 8, 7))
-    first = srv.submit(pid, "soft", 1024, 1024)  # 4096 tiles: keeps the one stream busy
+    first = srv.submit(pid, "soft", 1024, 1024)  # 4096 tiles: the one stream busy for 0.5 s
     time.sleep(0.01)
     small = [srv.submit(pid, "soft", 128, 128) for _ in range(2)]
     big = srv.submit(pid, "hard", 512, 512)      # 1024 tiles
