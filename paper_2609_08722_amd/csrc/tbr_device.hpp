@@ -158,10 +158,18 @@ __device__ __forceinline__ Chart chart(double x, double y, const StrokeRec& g) {
   return c;
 }
 
-// Distance whose parallel set has area Q, cancellation-free root of
-// pi s^2 + 2 l s = Q (Eq. back / Eq. fwd).
-__device__ __forceinline__ float area_to_dist(float q, const StrokeRec& g) {
-  return q * rcp(g.ell + hw_sqrt(fmaf(g.ell, g.ell, kPi * q)));
+// Distance whose parallel set has area Q: the cancellation-free root
+// s = Q / D of pi s^2 + 2 l s = Q, D = l + sqrt(l^2 + pi Q) (Eq. back /
+// Eq. fwd). As pi s + l = sqrt(l^2 + pi Q), D also gives the divisor of a
+// distance increment from sig to s: 2 l + pi (sig + s) = pi sig + D.
+struct Root {
+  float sig_o, d;
+};
+__device__ __forceinline__ Root area_root(float q, const StrokeRec& g) {
+  Root o;
+  o.d = g.ell + hw_sqrt(fmaf(g.ell, g.ell, kPi * q));
+  o.sig_o = q * rcp(o.d);
+  return o;
 }
 
 // sin(d) and cos(d) - 1 for d in [-pi/2, pi/2] (odd / even polynomials).
@@ -322,16 +330,20 @@ __device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, boo
   float q = backward ? (kFloor ? fmaxf(cq, g.floor_c) : cq) : fwd_area(c.sig, lf, two_ell);
   float num =
       backward ? (m.floored ? g.floor_c - c.sig * fmaf(kPi, c.sig, two_ell) : -lf.ar) : lf.ar;
+  float d;
   if constexpr (kPer) {
     const float X = fmaf(g.ell, g.ell, kPi * q);
     const float rs = __builtin_amdgcn_rsqf(X);
-    m.sig_o = q * rcp(g.ell + X * rs);
+    d = g.ell + X * rs;
+    m.sig_o = q * rcp(d);
     m.inv_per_o = 0.5f * rs;
   } else {
-    m.sig_o = area_to_dist(q, g);
+    const Root rt = area_root(q, g);
+    m.sig_o = rt.sig_o;
+    d = rt.d;
     m.inv_per_o = 0.f;
   }
-  float dsig = num * rcp(fmaf(kPi, c.sig + m.sig_o, two_ell));
+  float dsig = num * rcp(fmaf(kPi, c.sig, d));
   float dt = kTwoPi * c.w * dsig;
   float t_o = c.w * fmaf(kTwoPi, m.sig_o, two_ell);
   const float inv_sig_o = rcp(m.sig_o);
@@ -370,8 +382,9 @@ __device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, boo
 __device__ __forceinline__ Move psi_far(const Chart& c, const StrokeRec& g, const Leaf& lf) {
   const float two_ell = g.two_ell;
   const float q = back_area(c.sig, lf, two_ell);
-  const float sig_o = area_to_dist(q, g);
-  const float dsig = -lf.ar * rcp(fmaf(kPi, c.sig + sig_o, two_ell));
+  const Root rt = area_root(q, g);
+  const float sig_o = rt.sig_o;
+  const float dsig = -lf.ar * rcp(fmaf(kPi, c.sig, rt.d));
   const float inv_sig_o = rcp(sig_o);
   const float dth_cc = dsig * g.ell * (kPi - 2.f * c.th) * (c.inv_per * inv_sig_o);
   if (wave_all(c.th > 0.f && c.th + dth_cc > 0.f)) {
@@ -404,9 +417,10 @@ __device__ __forceinline__ Move regenerate(const Chart& c, const StrokeRec& g, c
   m.floored = false;
   const float X = fmaf(g.ell, g.ell, kPi * q);
   const float rs = __builtin_amdgcn_rsqf(X);
-  m.sig_o = q * rcp(g.ell + X * rs);
+  const float d = g.ell + X * rs;
+  m.sig_o = q * rcp(d);
   m.inv_per_o = 0.5f * rs;
-  const float dsig = lf.ar * rcp(fmaf(kPi, c.sig + m.sig_o, two_ell));
+  const float dsig = lf.ar * rcp(fmaf(kPi, c.sig, d));
   const float inv_sig_o = rcp(m.sig_o);
   const bool cap_in = c.th > 0.f;
   const float dth_cc = dsig * g.ell * (kPi - 2.f * c.th) * (c.inv_per * inv_sig_o);
@@ -512,7 +526,7 @@ __device__ __forceinline__ bool drops_backward(double& x, double& y, const Strok
 // centre c_j = m + f_j l e receives -(J - I) lambda; s^2 = A_l(r) / (16 pi)
 // receives v . lambda dk/d(s^2).
 struct DropsAdj {
-  float gmx, gmy, gphi, gell, gr;
+  float nmx, nmy, gphi, gell, gr;  // nmx, nmy: the centre's, negated (as VjpOut's)
 };
 
 __device__ __forceinline__ DropsAdj drops_replay(double& x, double& y, const StrokeRec& g,
@@ -595,8 +609,8 @@ __device__ __forceinline__ DropsAdj drops_replay(double& x, double& y, const Str
     y += (double)Dy;
   }
   DropsAdj o;
-  o.gmx = -Sx;
-  o.gmy = -Sy;
+  o.nmx = Sx;
+  o.nmy = Sy;
   // c_j = m + f_j l e: dc_j/dphi = f_j l n, dc_j/dl = f_j e
   o.gphi = -g.ell * fmaf(-Fx, g.se, Fy * g.ce);
   // s^2 = A_l(r) / (16 pi): d/dl = 2 r / (16 pi), d/dr = P_l(r) / (16 pi)
@@ -702,7 +716,9 @@ struct VjpIn {
 
 struct VjpOut {
   float gx, gy;                          // lambda^x_i
-  float gmx, gmy, gphi, gell, gr;        // stroke contributions
+  // stroke contributions; nmx, nmy are the centre's NEGATED (the point's
+  // adjoint increment itself: the block sums flip their sign once per stroke)
+  float nmx, nmy, gphi, gell, gr;
 };
 
 // The inert-mark model R_U (psi = id, Def. inert-mark): the point never
@@ -722,8 +738,8 @@ __device__ __forceinline__ VjpOut vjp_cover_only(const Chart& c, const StrokeRec
   const float gy = fmaf(ssb, g.se, shb * g.ce);
   o.gx = 0.f;
   o.gy = 0.f;
-  o.gmx = -gx;
-  o.gmy = -gy;
+  o.nmx = gx;
+  o.nmy = gy;
   // turning the stroke by dphi changes sigma as turning the point by -dphi
   o.gphi = zw * (c.sgs * c.sgh) * (fminf(c.S, g.hl) * c.cs);
   o.gell = -0.5f * eb;
@@ -809,8 +825,8 @@ __device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, f
   const float dy = fmaf(ssd, g.se, shd * g.ce);
   o.gx = lx + dx;
   o.gy = ly + dy;
-  o.gmx = -dx;
-  o.gmy = -dy;
+  o.nmx = dx;
+  o.nmy = dy;
   return o;
 }
 
@@ -859,8 +875,8 @@ __device__ __forceinline__ VjpOut vjp_far(const VjpIn& v, const StrokeRec& g, fl
   const float dy = fmaf(ssd, g.se, shd * g.ce);
   o.gx = lx + dx;
   o.gy = ly + dy;
-  o.gmx = -dx;
-  o.gmy = -dy;
+  o.nmx = dx;
+  o.nmy = dy;
   return o;
 }
 

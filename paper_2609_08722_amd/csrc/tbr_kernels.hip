@@ -491,7 +491,10 @@ __device__ __forceinline__ float row_sums8(const float (&v)[8], int lane) {
   return t + dpp_mov<kRowRor8>(t);
 }
 
-// Same result when values 5..7 are zero (strokes far from the wave).
+// Same result when values 5..7 are zero (strokes far from the wave). The
+// lanes that end with value index 4..7 (lane bit 0 set) only ever combine
+// with each other, so the stage-1 sums of values 1..3 may stand in for the
+// missing 5..7 there; one select zeroes the lanes of values 5..7 at the end.
 __device__ __forceinline__ float row_sums5(const float (&v)[5], int lane) {
   const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
   float u[4];
@@ -501,10 +504,7 @@ __device__ __forceinline__ float row_sums5(const float (&v)[5], int lane) {
     u[0] = b0 ? r1 : r0;
   }
 #pragma unroll
-  for (int j = 1; j < 4; ++j) {
-    float r0 = v[j] + dpp_mov<kQuadXor1>(v[j]);
-    u[j] = b0 ? 0.f : r0;
-  }
+  for (int j = 1; j < 4; ++j) u[j] = v[j] + dpp_mov<kQuadXor1>(v[j]);
   float w[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -515,7 +515,8 @@ __device__ __forceinline__ float row_sums5(const float (&v)[5], int lane) {
   float r0 = w[0] + dpp_mov<kRowShl4>(w[0]);
   float r1 = w[1] + dpp_mov<kRowShr4>(w[1]);
   float t = b2 ? r1 : r0;
-  return t + dpp_mov<kRowRor8>(t);
+  t += dpp_mov<kRowRor8>(t);
+  return (b0 && (b1 || b2)) ? 0.f : t;
 }
 
 __device__ __forceinline__ int value_index_of_lane(int lane) {
@@ -619,7 +620,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           float ta = t * cv.alpha;
           lt = fmaf(cv.alpha, dlt, lt);  // (1 - alpha) lt + alpha lc
           VjpOut vo = vjp_cover_only(ca, g, cv, mu);
-          float v[8] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
+          float v[8] = {vo.nmx, vo.nmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
           tot = row_sums8(v, lane);
         }
         if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
@@ -631,7 +632,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           float s = 0.f;
 #pragma unroll
           for (int q = 0; q < 16; ++q) s += lds[buf][q][j][vv];
-          prow[(size_t)(c0 + j) * 8 + vv] = s;
+          prow[(size_t)(c0 + j) * 8 + vv] = vv < 2 ? -s : s;  // the centre's sign
         }
       }
     }
@@ -666,7 +667,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           te = (int)ckt.y;
         }
         const DropsAdj da = drops_replay(x, y, g, pop || ck, lx, ly);
-        float v[8] = {da.gmx, da.gmy, da.gphi, da.gell, da.gr, 0.f, 0.f, 0.f};
+        float v[8] = {da.nmx, da.nmy, da.gphi, da.gell, da.gr, 0.f, 0.f, 0.f};
         Chart ca;
         chart_dist(x, y, g, ca);
         if (!wave_all(is_far<false>(ca.sig, uniform_leaf(g), g))) {
@@ -683,10 +684,10 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           const float ta = t * cv.alpha;
           lt = fmaf(cv.alpha, dlt, lt);  // (1 - alpha) lt + alpha lc
           const VjpOut vo = vjp_cover_only(ca, g, cv, mu);
-          lx -= vo.gmx;  // + mu d alpha / dx at x_i
-          ly -= vo.gmy;
-          v[0] += vo.gmx;
-          v[1] += vo.gmy;
+          lx += vo.nmx;  // + mu d alpha / dx at x_i
+          ly += vo.nmy;
+          v[0] += vo.nmx;
+          v[1] += vo.nmy;
           v[2] += vo.gphi;
           v[3] += vo.gell;
           v[4] += vo.gr;
@@ -704,7 +705,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           float s = 0.f;
 #pragma unroll
           for (int q = 0; q < 16; ++q) s += lds[buf][q][j][vv];
-          prow[(size_t)(c0 + j) * 8 + vv] = s;
+          prow[(size_t)(c0 + j) * 8 + vv] = vv < 2 ? -s : s;  // the centre's sign
         }
       }
     }
@@ -786,7 +787,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
         }
         lx = vo.gx;
         ly = vo.gy;
-        float v[5] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr};
+        float v[5] = {vo.nmx, vo.nmy, vo.gphi, vo.gell, vo.gr};
         const float tot = row_sums5(v, lane);
         if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
       }
@@ -885,7 +886,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
         VjpOut vo = vjp_step<true, kC>(vi, g, lx, ly, mu, lf);
         lx = vo.gx;
         ly = vo.gy;
-        float v[8] = {vo.gmx, vo.gmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
+        float v[8] = {vo.nmx, vo.nmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
         tot = row_sums8(v, lane);
         if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
         ++j;
@@ -898,7 +899,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
         float s = 0.f;
 #pragma unroll
         for (int q = 0; q < 16; ++q) s += lds[buf][q][j][vv];
-        prow[(size_t)(c0 + j) * 8 + vv] = s;
+        prow[(size_t)(c0 + j) * 8 + vv] = vv < 2 ? -s : s;  // the centre's sign
       }
     }
   }

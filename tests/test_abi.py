@@ -52,8 +52,9 @@ def test_workspace_sizes_grow_with_tape(lib):
     a = lib.tbr_render_workspace_bytes(C.byref(o), 50, L.TBR_SOFT, 0)
     b = lib.tbr_render_workspace_bytes(C.byref(o), 50, L.TBR_SOFT, 1)
     P = 64 * 64
-    # tape: nrec + ckpt (1 + 49 // 16 = 4 states of 16 B) + side (4 slots x 12 B)
-    assert b - a >= P * (4 + 4 * 16 + 4 * 12)
+    # tape: nrec (4 B) + checkpoints (1 + 49 // 16 = 4 states of 16 B position
+    # + 8 B transmittance) + side table (4 slots x (4 B index + 16 B position))
+    assert b - a >= P * (4 + 4 * 24 + 4 * 20)
     assert lib.tbr_render_workspace_bytes(None, 50, L.TBR_SOFT, 0) == 0
     assert lib.tbr_backward_workspace_bytes(C.byref(o), 50, 8) >= 16 * (51 * 8 * 4)
     assert lib.tbr_fit_workspace_bytes(C.byref(o), 50, 8) > b

@@ -125,9 +125,9 @@ def test_drop_closed_form(orc, c):
 
 
 def test_first_mode_widens_the_flank_and_shortens_the_tips(orc):
-    """Eq. profile's first mode is +1 at the flank midpoints and -1 at the
-    tips: with c_1 > 0 the deposit reaches past r across the middle of the
-    segment and stops short of r beyond its ends."""
+    """Sec. 4, Eq. profile: with c_1 > 0 the profile g is above 1 across the
+    middle of the segment and below 1 beyond its ends, so the deposit reaches
+    past r beside the segment and stops short of r past its ends."""
     ell, r, c1 = 0.10, 0.03, 0.3
     g = stroke_for(ell, r)
     prog = {"cx": g[:1], "cy": g[1:2], "angle": g[2:3], "length": g[3:4],
