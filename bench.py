@@ -31,23 +31,29 @@ if ROOT not in sys.path:
 
 # MI355X published FP32 vector peak: 256 CUs x 2.4 GHz x 256 FLOP/clock/CU.
 PEAK_FP32_FLOPS = 157.3e12
-# Algorithmic FP operations per pixel-stroke, counted item by item from the
-# formulas the kernels evaluate (FMA = 2; every other FP32/FP64 operation,
-# incl. abs, compare, select, min/max, conversion and transcendental, = 1;
-# a sign folded into an operand = 0). These are the counts of a stroke far
-# from the wave (coverage below 7e-13: no coverage or colour terms), >99% of
-# pixel-strokes here, whose rotation is small and, in the replay, whose wave
-# lies on the stroke's cap (the common case); other steps do more work, so
-# the counts are a lower bound. The path is ALU-bound: HBM traffic is
-# ~0.45 B per pixel-stroke.
-FLOPS_FWD = 147      # soft forward step: chart 62, far vote 1, psi 72 (no floor), advance 12
-FLOPS_REPLAY = 213   # replay step: chart 62, vote 1, Phi 54, new point 4, advance 10,
-                     # VJP 63, wave reduction 19
+# Algorithmic FP operations per pixel-stroke of the common step: a stroke far
+# from every lane of the wave (coverage below 7e-13: no coverage or colour
+# terms), >99% of pixel-strokes here, whose wave lies on the stroke's cap and
+# turns by less than 1/16 rad. Counted over that step's compiled instructions
+# (FMA = 2; every other floating-point add, mul, min/max, compare, select,
+# conversion, FP64 add, transcendental and DPP add = 1; register moves, sign
+# inserts, integer and scalar work = 0). Other steps do more work, so the
+# counts are a lower bound. The path is ALU-bound: HBM traffic is ~0.45 B per
+# pixel-stroke.
+FLOPS_FWD = 117      # soft forward far step: chart, far vote, psi (cap to cap), FP64 advance
+FLOPS_REPLAY = 222   # replay far step: chart, far vote, Phi (cap to cap), VJP, row sums,
+                     # FP64 advance
 # HBM bytes per k_fit_fused launch at the bench workload, from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
 # in the same runs; valid only for the kernel sources it was measured on
 # (or sources whose k_fit_fused<0> compiles to the same code).
 TRAFFIC = {"sha": "ea0ef1fd162f76dd", "bytes": 346.5e6 + 572.8e6}
+# Wave-level instruction counts per k_fit_fused<0> launch at the bench
+# workload (rocprofv3 --pmc, per-dispatch averages), for the same sources
+# only: SQ_INSTS_VALU_{FMA,ADD,MUL}_F32, SQ_INSTS_VALU_TRANS_F32 and
+# SQ_INSTS_VALU. Each wave instruction does 64 lane operations.
+COUNTERS = {"sha": None, "fma_f32": None, "add_f32": None, "mul_f32": None,
+            "trans_f32": None, "valu": None}
 
 
 def kernel_sha():
@@ -535,6 +541,17 @@ def main():
                 "peak": PEAK_FP32_FLOPS / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_FLOPS, "traffic": traffic,
                 "flops_per_pixel_stroke": flops, "launch_ms": ms_fused}
+    # the same launch's FP32 add/mul/FMA as the hardware counted them (all
+    # 64 lanes of each wave instruction), against the same peak
+    if COUNTERS["sha"] == kernel_sha() and w.name == "fit1024x1024_n2000":
+        c = COUNTERS
+        ctr = 64.0 * (2.0 * c["fma_f32"] + c["add_f32"] + c["mul_f32"]) / (ms_fused * 1e-3)
+        roofline["counter_achieved"] = ctr / 1e12
+        roofline["counter_frac"] = ctr / PEAK_FP32_FLOPS
+        roofline["valu_per_wave_stroke"] = c["valu"] / (P / 64 * N)
+    else:
+        roofline["counter_achieved"] = roofline["counter_frac"] = None
+        roofline["valu_per_wave_stroke"] = None
 
     # the two halves as separate kernels (the render with tape and the
     # replay adjoint behind tbr_render / tbr_render_backward), same program
