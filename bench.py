@@ -180,8 +180,8 @@ def transports_benchmark(w, prog, target, reps=5):
     """The benchmark program under each transport the library implements:
     the capsule map, its calibrated coupling (per-stroke c_k ~ U(-0.15,
     0.15)), the inert-mark model R_U and the sixteen-drop R_D. Soft and hard
-    render time (median of reps, HIP events), and for the first three the
-    fused fit step (tbr_fit_step), pixel-strokes per second."""
+    render time (median of reps, HIP events) and the fit step
+    (tbr_fit_step), pixel-strokes per second."""
     import torch
     from paper_2609_08722_amd import api, synth
     dp = api.to_device(prog)
@@ -208,14 +208,14 @@ def transports_benchmark(w, prog, target, reps=5):
                      side_slots=23, **kw)
         r = {"soft_ms": timed(lambda: api.render(dp, o, "soft")),
              "hard_ms": timed(lambda: api.render(dp, o, "hard"))}
-        if name != "drops16":
-            fit = api.FitState({f: v.clone() for f, v in dp.items()}, o,
-                               api.Adam(r_lo=0.002, r_hi=0.02, l_max=0.08))
-            for _ in range(2):
-                fit.step_checked(target, headroom=8)
-            r["fit_step_ms"] = timed(lambda: fit.step(target))
-            r["fit_pixel_strokes_per_s"] = P * N / (r["fit_step_ms"] * 1e-3)
-            del fit
+        fit = api.FitState({f: v.clone() for f, v in dp.items()}, o,
+                           api.Adam(r_lo=0.002, r_hi=0.02, l_max=0.08))
+        for _ in range(2):
+            fit.step_checked(target, headroom=8)
+        r["fit_step_ms"] = timed(lambda: fit.step(target))
+        r["fit_pixel_strokes_per_s"] = P * N / (r["fit_step_ms"] * 1e-3)
+        r["side_slots"] = fit.opts.side_slots
+        del fit
         r["soft_pixel_strokes_per_s"] = P * N / (r["soft_ms"] * 1e-3)
         out[name] = r
         torch.cuda.empty_cache()
