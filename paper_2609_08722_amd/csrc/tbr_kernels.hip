@@ -932,11 +932,19 @@ __global__ void __launch_bounds__(256)
 // tile (each lane reads back only its own tape). Partial rows are indexed by
 // tile, so the order in which blocks take tiles cannot change any sum.
 // ---------------------------------------------------------------------------
-// The forward and the replay share one register allocation here; asking for
-// 5 waves per SIMD (96 VGPRs, instead of 111 at 4 waves) spills only values
-// that live across a tile or a 16-stroke chunk, never inside a stroke loop.
+// The forward and the replay share one register allocation here, so the
+// launch bound (waves per SIMD) trades registers for occupancy per
+// transport, as measured at 1024^2 x 2000 (bitwise the same results at
+// every bound): the capsule map at 6 waves (80 VGPRs; the few spills are of
+// values that live across a tile or a 16-stroke chunk) runs 7% faster than
+// at 5 (92 VGPRs, no spill) and 3% faster than at 7; the coupled map, with
+// more live values, is fastest at 5; R_D at 7 (72 VGPRs).
 template <int kT>
-__global__ void __launch_bounds__(256, 5) k_fit_fused(FitJobsK jobs, int* __restrict__ cursor) {
+constexpr int kFusedWaves = kT == kCoupled ? 5 : (kT == kDrops ? 7 : 6);
+
+template <int kT>
+__global__ void __launch_bounds__(256, kFusedWaves<kT>) k_fit_fused(FitJobsK jobs,
+                                                                   int* __restrict__ cursor) {
   __shared__ ReduceLds lds;
   __shared__ float red[256];
   __shared__ int item_s;
