@@ -127,6 +127,14 @@ __device__ __forceinline__ void chart_dist(double x, double y, const StrokeRec& 
   c.sig = hw_sqrt(fmaf(c.H, c.H, c.E * c.E));
 }
 
+// The cap angle alone, for a point off the segment (sigma > 0): all that a
+// far step which stays on the cap needs of the chart's angle part.
+__device__ __forceinline__ float far_theta(const Chart& c) {
+  const float hi = fmaxf(c.E, c.H), lo = fminf(c.E, c.H);
+  const float t = atan01(lo * rcp(hi));
+  return c.E > c.H ? kHalfPi - t : t;
+}
+
 template <bool kFar = false>
 __device__ __forceinline__ void chart_angle(const StrokeRec& g, Chart& c) {
   if constexpr (kFar) {
@@ -200,6 +208,35 @@ __device__ __forceinline__ void sincosm1_small(float d, float& s, float& cm1) {
   float u = d * d;
   s = d * fmaf(u, fmaf(u, 1.f / 120.f, -1.f / 6.f), 1.f);
   cm1 = u * fmaf(u, fmaf(u, -1.f / 720.f, 1.f / 24.f), -0.5f);
+}
+
+// Below |d| = 2^-12, sin d = d and cos d - 1 = -d^2 / 2 to within d^3 / 6 <
+// 2.4e-12 and d^4 / 24 < 1.5e-16: relative errors below 1e-8, under FP32
+// rounding. A far stroke turns a point's cap angle by about 1e-5 rad, so
+// almost every wave of a far step takes this first-order rotation.
+constexpr float kTinyTurn = 2.44140625e-4f;  // 2^-12
+
+// (R(d) - I) p for p = (a, b) in the folded frame, where R(d) turns the
+// cap angle (measured from the normal towards the segment direction) by d:
+// returns (a (cos d - 1) + b sin d, b (cos d - 1) - a sin d). kTiny: |d| <
+// kTinyTurn for every lane (first order; see above).
+template <bool kTiny>
+__device__ __forceinline__ void turn_increment(float d, float a, float b, float& ra,
+                                               float& rb) {
+  if constexpr (kTiny) {
+    const float hd = -0.5f * d;
+    ra = d * fmaf(a, hd, b);
+    rb = d * fmaf(b, hd, -a);
+  } else {
+    float sd, cm1;
+    if (wave_all(fabsf(d) < kSmallTurn)) {
+      sincosm1_small(d, sd, cm1);
+    } else {
+      sincosm1(d, sd, cm1);
+    }
+    ra = fmaf(a, cm1, b * sd);
+    rb = fmaf(b, cm1, -(a * sd));
+  }
 }
 
 // What the stroke inserts along the leaf of a charted point. Uniform
@@ -372,37 +409,6 @@ __device__ __forceinline__ Move displace(const Chart& c, const StrokeRec& g, boo
   m.dcos = dcos;
   flank_part(c, g, m);
   return m;
-}
-
-// psi of a point beyond the stroke's far margin (no floor, uniform
-// insertion), displacement only, for the forward traces' far steps. psi
-// moves a point along its leaf towards the segment, so a point on a cap
-// either stays on it (th + dth > 0 with the cap-to-cap dth) or reaches the
-// flank; a wave whose lanes all stay takes the cap-to-cap formulas alone.
-__device__ __forceinline__ Move psi_far(const Chart& c, const StrokeRec& g, const Leaf& lf) {
-  const float two_ell = g.two_ell;
-  const float q = back_area(c.sig, lf, two_ell);
-  const Root rt = area_root(q, g);
-  const float sig_o = rt.sig_o;
-  const float dsig = -lf.ar * rcp(fmaf(kPi, c.sig, rt.d));
-  const float inv_sig_o = rcp(sig_o);
-  const float dth_cc = dsig * g.ell * (kPi - 2.f * c.th) * (c.inv_per * inv_sig_o);
-  if (wave_all(c.th > 0.f && c.th + dth_cc > 0.f)) {
-    Move m;
-    float sd, cdm1;
-    if (wave_all(fabsf(dth_cc) < kSmallTurn)) {
-      sincosm1_small(dth_cc, sd, cdm1);
-    } else {
-      sincosm1(dth_cc, sd, cdm1);
-    }
-    const float dsin = fmaf(c.sn, cdm1, c.cs * sd);
-    const float dcos = fmaf(c.cs, cdm1, -(c.sn * sd));
-    m.dS = fmaf(dsig, c.sn + dsin, c.sig * dsin);
-    m.dH = fmaf(dsig, c.cs + dcos, c.sig * dcos);
-    m.floored = false;
-    return m;
-  }
-  return displace<false, false>(c, g, true, lf);
 }
 
 // Phi of a charted point with 1 / P_l(sig_o), for the replay's common steps:
@@ -631,6 +637,50 @@ __device__ __forceinline__ void step_by(double& x, double& y, float a, float b,
 __device__ __forceinline__ void advance(double& x, double& y, const Chart& c, const Move& m,
                                         const StrokeRec& g) {
   step_by(x, y, c.sgs * m.dS, c.sgh * m.dH, g);
+}
+
+// psi of a point beyond the stroke's far margin (no floor), for the forward
+// traces' far steps, advanced into the FP64 state. The chart needs the
+// distance part; th is its cap angle (kAngle: the chart holds the angle
+// part too, as the coupled traces chart in full before their vote).
+//
+// psi moves a point along its leaf towards the segment: a point on a cap
+// stays on it when th + dth > 0 with the cap-to-cap increment
+//   dth = dsig l (pi - 2 th) / (P_l(sig) sig_o)
+// (dth <= 0, so this also rules out the flank, th = 0), and there the new
+// point is the old one turned by dth about the cap's centre and scaled by
+// sig_o / sig = 1 + k, k = dsig / sig. Both come from one reciprocal each:
+//   k = -A / (sig (pi sig + D))  (Eq. back: dsig = -A / (pi sig + D) with
+//       D = l + sqrt(l^2 + pi q), q = A_l(sig) - A, the area root's
+//       denominator),
+//   dth = k l (pi - 2 th) / (P_l(sig) (1 + k)),
+// and with the folded offset p = (E, H) from the cap's centre the
+// displacement is k (p + r) + r, r = (R(dth) - I) p: no 1 / sigma, no sine
+// and cosine of th. Beyond the margin q = A_l(sig) - A has no cancellation
+// (sig - r >= 28 wd), so it is formed unfactored. A wave with a lane that
+// reaches the flank takes the general map.
+template <bool kAngle>
+__device__ __forceinline__ void psi_far_advance(double& x, double& y, const Chart& c, float th,
+                                                const StrokeRec& g, const Leaf& lf) {
+  const float q = fmaf(c.sig, fmaf(kPi, c.sig, g.two_ell), -lf.ar);
+  const float D = g.ell + hw_sqrt(fmaf(g.ell, g.ell, kPi * q));
+  const float k = -lf.ar * rcp(c.sig * fmaf(kPi, c.sig, D));
+  const float per = fmaf(kTwoPi, c.sig, g.two_ell);
+  const float dth = (k * g.ell) * fmaf(-2.f, th, kPi) * rcp(per * (1.f + k));
+  if (wave_all(th + dth > 0.f)) {
+    float ra, rb;
+    if (wave_all(fabsf(dth) < kTinyTurn)) {
+      turn_increment<true>(dth, c.E, c.H, ra, rb);
+    } else {
+      turn_increment<false>(dth, c.E, c.H, ra, rb);
+    }
+    const float dS = fmaf(k, c.E + ra, ra), dH = fmaf(k, c.H + rb, rb);
+    step_by(x, y, c.sgs * dS, c.sgh * dH, g);
+    return;
+  }
+  Chart cf = c;
+  if constexpr (!kAngle) chart_angle<true>(g, cf);
+  advance(x, y, cf, displace<false, false>(cf, g, true, lf), g);
 }
 
 // Soft coverage alpha = sigmoid((edge - sigma) / wd) with alpha <= 1 - 1e-7

@@ -206,9 +206,9 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
         ++nrec;
       }
     } else if constexpr (kT != kInert) {
-      Move mv = kFloor ? displace<false, true>(c, g, true, lf) : psi_far(c, g, lf);
-      if constexpr (kFloor) {  // record where the floor binds
-        if (mv.floored) {
+      if constexpr (kFloor) {
+        Move mv = displace<false, true>(c, g, true, lf);
+        if (mv.floored) {  // record where the floor binds
           if (write_tape && nrec < tape.side_slots) {
             size_t o = (size_t)nrec * P + id.p;
             tape.side_idx[o] = i;
@@ -216,8 +216,10 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
           }
           ++nrec;
         }
+        advance(x, y, c, mv, g);
+      } else {
+        psi_far_advance<kT == kCoupled>(x, y, c, kT == kCoupled ? c.th : far_theta(c), g, lf);
       }
-      advance(x, y, c, mv, g);
     }
   };
   int i = n - 1;
@@ -256,7 +258,6 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
           near = true;
           break;
         }
-        if constexpr (kT == kCapsule) chart_angle<true>(g, c);
       }
       transport(i, c, g, lf, std::integral_constant<bool, false>{});
     }
@@ -316,8 +317,7 @@ __device__ __forceinline__ void hard_pixel(const StrokeRec* __restrict__ recs,
         // Every lane still tracing lies beyond the stroke's far margin: none
         // can hit it, and psi's floor cannot bind there.
         if (wave_all(is_far<kT == kCoupled>(c.sig, lf, g))) {
-          if constexpr (kT == kCapsule) chart_angle<true>(g, c);
-          advance(x, y, c, psi_far(c, g, lf), g);
+          psi_far_advance<kT == kCoupled>(x, y, c, kT == kCoupled ? c.th : far_theta(c), g, lf);
           continue;
         }
       }
