@@ -66,6 +66,12 @@ __device__ __forceinline__ bool wave_all(bool p) {
   return __builtin_amdgcn_ballot_w64(p) == __builtin_amdgcn_read_exec();
 }
 __device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+// p && q on every active lane: the two ballots are combined in scalar
+// registers (a vector && would first turn the compare results into 0 / 1).
+__device__ __forceinline__ bool wave_all2(bool p, bool q) {
+  return (__builtin_amdgcn_ballot_w64(p) & __builtin_amdgcn_ballot_w64(q)) ==
+         __builtin_amdgcn_read_exec();
+}
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -880,54 +886,92 @@ __device__ __forceinline__ VjpOut vjp_step(const VjpIn& v, const StrokeRec& g, f
   return o;
 }
 
-// vjp_step<false> for the replay's common step under uniform insertion: the
-// stroke is far from the wave (no coverage terms) and no lane is floored.
-// kCapCap: every lane of the wave lies on the cap at both points (tf = l/2,
-// dtf = 0), the case of almost every wave a stroke is far from.
-template <bool kCapCap>
-__device__ __forceinline__ VjpOut vjp_far(const VjpIn& v, const StrokeRec& g, float lx, float ly) {
-  VjpOut o;
+// The replay's common step when every lane of the wave lies on the stroke's
+// cap (E > 0) beyond its far margin, under uniform insertion: regenerates
+// x_i = Phi_i(x_{i-1}) into the FP64 state, replaces lambda^x_{i-1} (lx, ly)
+// by lambda^x_i and returns the stroke's contributions (the centre's
+// negated, phi, l, r) in v.
+//
+// In polar coordinates about the cap's centre c = m + sgs (l/2) e the chart
+// point a = x_{i-1} sits at (sig_a, th_a), and Phi moves it along its leaf
+// (fixed fraction w) to b = x_i at (sig_b, th_b), sig_b = sig_a (1 + k),
+// th_b = th_a + dth (Eq. fwd; the forward far step's formulas with the
+// inserted area's sign flipped). With kap = 2 pi w - th = l (pi - 2 th) /
+// P_l(sig) at either point, u = (P_b - P_a) / P_a and v = (P_b - P_a) / P_b,
+// psi's vector-Jacobian product (Eq. adjstep) takes lambda_a, whose radial
+// and tangential parts at a are ao and tpb, to lambda_b with
+//   tangential part at b  tpb P_a / P_b = tpb - tpb v,
+//   radial part at b      ao + ao u + tpb (dth (1 - v) + kap_a (u + v)),
+// and the area's adjoint is cb = (ao + tpb kap_a) / P_a. Every difference
+// between the two points is a product of increments, so nothing cancels.
+// The stroke's contributions (Eq. adjparam):
+//   centre  lambda_a - lambda_b (translation invariance; returned negated),
+//   r       -cb P_l(r),
+//   l       2 cb (dsig - r) + tpb v (2 w - 1/2) - (lambda_b - lambda_a) . e_c / 2
+//           (the area root, the fraction, and the cap's centre moving by
+//           e_c / 2 = sgs e / 2),
+//   phi     rotation invariance about m, split at c: the lever c - m turning
+//           with the stroke gives -sgs sgh (l/2) dh (dh the folded normal part
+//           of lambda_b - lambda_a), and the turn about c gives sgs sgh
+//           (sig_b tpb_b - sig_a tpb_a) = sgs sgh (l / pi) tpb v, because
+//           sig_a P_b - sig_b P_a = -2 l dsig.
+__device__ __forceinline__ void far_cap_step(double& x, double& y, float& lx, float& ly,
+                                             const Chart& a, const StrokeRec& g, float (&v)[5]) {
+  constexpr float kInvPi = 0.318309886183790671538f;
+  const float th = far_theta(a);
+  // Phi (Eq. fwd): A_l(sig_b) = A_l(sig_a) + A_l(r); with D = l + sqrt(l^2 +
+  // pi q) the root's denominator, dsig = A / (pi sig_a + D), and
+  // sqrt(l^2 + pi q) = P_l(sig_b) / 2
+  const float q = fmaf(a.sig, fmaf(kPi, a.sig, g.two_ell), g.ar);
+  const float X = fmaf(g.ell, g.ell, kPi * q);
+  const float rs = __builtin_amdgcn_rsqf(X);  // 2 / P_l(sig_b)
+  const float pd = fmaf(kPi, a.sig, fmaf(X, rs, g.ell));
+  const float K = rcp(a.sig * pd);
+  const float k = g.ar * K;  // dsig / sig_a
+  const float dsig = k * a.sig;
+  const float inv_sa = pd * K;
+  const float Pa = fmaf(kTwoPi, a.sig, g.two_ell);
+  const float R = rcp(Pa * (1.f + k));
+  const float inv_Pa = (1.f + k) * R;
+  const float Ath = g.ell * fmaf(-2.f, th, kPi);
+  const float kap = Ath * inv_Pa;  // 2 pi w - th_a
+  const float dth = Ath * k * R;   // th_b - th_a = dsig kap_a / sig_b
+  float ra, rb;                    // (R(dth) - I) (E, H)
+  if (wave_all(fabsf(dth) < kTinyTurn)) {
+    turn_increment<true>(dth, a.E, a.H, ra, rb);
+  } else {
+    turn_increment<false>(dth, a.E, a.H, ra, rb);
+  }
+  step_by(x, y, a.sgs * fmaf(k, a.E + ra, ra), a.sgh * fmaf(k, a.H + rb, rb), g);
+  // unit vectors (sin th, cos th) at a and b, and their increments
+  const float sn_a = a.E * inv_sa, cs_a = a.H * inv_sa;
+  const float dsn = ra * inv_sa, dcs = rb * inv_sa;
+  const float sn_b = sn_a + dsn, cs_b = cs_a + dcs;
+  // lambda_a in the folded frame at a: radial ao, tangential tpb
   const float ge = fmaf(lx, g.ce, ly * g.se);
   const float gn = fmaf(ly, g.ce, -(lx * g.se));
-  const float sbp = v.sgs * ge, hbp = v.sgh * gn;
-  const float tpb = fmaf(sbp, v.cs_o, -(hbp * v.sn_o));
-  const float ao = fmaf(sbp, v.sn_o, hbp * v.cs_o);
-  const float tw = kTwoPi * v.w;
-  const float cb = fmaf(tpb, tw - v.th_o, ao) * v.inv_p0;
-  const float p1 = fmaf(kTwoPi, v.sig, g.two_ell);
-  const float t1 = kTwoPi * v.dsig;
-  const float du = v.dsig * v.inv_p1;
-  const float u = kTwoPi * du;
-  const float dT = tpb * u;
-  o.gr = -(cb * g.per_r);
-  const float kap = v.th - tw;
-  const float dsg = fmaf(kap, dT, -fmaf(v.dth, tpb, cb * t1));
-  const float de = fmaf(dsg, v.sn, fmaf(dT, v.cs, -fmaf(ao, v.dsin, tpb * v.dcos)));
-  const float dh = fmaf(dsg, v.cs, fmaf(-dT, v.sn, fmaf(-ao, v.dcos, tpb * v.dsin)));
-  o.gell = fmaf(0.5f, dT - de, fmaf(-2.f * v.w, dT, 2.f * cb * (-v.dsig - g.r)));
-  float br = fmaf(v.dth, v.cs_o, -v.dsin);
-  br = fmaf(kap, v.dcos, br);
-  br = fmaf(-u, fmaf(kap, v.cs, -v.sn), br);
-  float ang;
-  if constexpr (kCapCap) {
-    const float Y = fmaf(t1, v.cs_o, p1 * v.dcos);
-    const float X = fmaf(g.hl, br, -g.two_ell * du);
-    ang = fmaf(cb * g.hl, Y, tpb * X);
-  } else {
-    const float Y = fmaf(t1 * v.tf_o, v.cs_o, p1 * fmaf(v.dtf, v.cs_o, v.tf * v.dcos));
-    float X = fmaf(v.tf, br, -g.two_ell * du);
-    X = fmaf(v.dtf, fmaf(v.th_o - tw, v.cs_o, -v.sn_o), X);
-    ang = fmaf(cb, Y, tpb * X);
-  }
-  o.gphi = (v.sgs * v.sgh) * ang;
-  const float ssd = v.sgs * de, shd = v.sgh * dh;
+  const float sbp = a.sgs * ge, hbp = a.sgh * gn;
+  const float ao = fmaf(sbp, sn_a, hbp * cs_a);
+  const float tpb = fmaf(sbp, cs_a, -(hbp * sn_a));
+  const float cb = fmaf(tpb, kap, ao) * inv_Pa;
+  const float vb = (kPi * dsig) * rs;        // (P_b - P_a) / P_b
+  const float u = (kTwoPi * dsig) * inv_Pa;  // (P_b - P_a) / P_a
+  const float dtan = -tpb * vb;
+  const float drad = fmaf(tpb, fmaf(kap, u + vb, fmaf(-dth, vb, dth)), ao * u);
+  // lambda_b - lambda_a in the folded frame, then unfolded
+  const float de = fmaf(drad, sn_b, fmaf(dtan, cs_b, fmaf(ao, dsn, tpb * dcs)));
+  const float dh = fmaf(drad, cs_b, fmaf(-dtan, sn_b, fmaf(ao, dcs, -(tpb * dsn))));
+  const float ssd = a.sgs * de, shd = a.sgh * dh;
   const float dx = fmaf(ssd, g.ce, -(shd * g.se));
   const float dy = fmaf(ssd, g.se, shd * g.ce);
-  o.gx = lx + dx;
-  o.gy = ly + dy;
-  o.nmx = dx;
-  o.nmy = dy;
-  return o;
+  lx += dx;
+  ly += dy;
+  v[0] = dx;
+  v[1] = dy;
+  v[2] = -(a.sgs * a.sgh) * fmaf(g.ell * kInvPi, dtan, g.hl * dh);
+  // 2 w - 1/2 = (th_a + kap_a) / pi - 1/2
+  v[3] = fmaf(-0.5f, de, fmaf(-dtan, fmaf(th + kap, kInvPi, -0.5f), 2.f * cb * (dsig - g.r)));
+  v[4] = -(cb * g.per_r);
 }
 
 }  // namespace tbr

@@ -537,6 +537,15 @@ constexpr int kChunk = 16;
 // chunk, padded so the 4 rows of a wave write distinct banks][value].
 using ReduceLds = float[2][16][kChunk + 1][8];
 
+// The smallest stroke index at which some lane of the wave pops a side-table
+// record (top_idx < 0: the lane has none left), or INT_MAX: wave-uniform, so
+// the replay's common steps test it with a scalar compare.
+__device__ __forceinline__ int wave_next_pop(int top_idx) {
+  int m = top_idx >= 0 ? top_idx : 0x7fffffff;
+  for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off));
+  return __builtin_amdgcn_readfirstlane(m);
+}
+
 // The replay of one 16x16 tile by the whole block (all 256 threads must
 // call it). lcr, lcg, lcb: this lane's dL/dR; prow: the tile's partial row
 // [n + 1][8] (row n = background colour gradient).
@@ -712,82 +721,85 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
     return;
   }
   constexpr bool kC = kT == kCoupled;
+  // the next step that some lane of the wave loads (a checkpoint or a pop)
+  int next_pop = wave_next_pop(top_idx);
+  int next_stop = min(next_ck, next_pop);
   for (int c0 = 0; c0 < n; c0 += kChunk) {
     const int buf = (c0 / kChunk) & 1;
     const int cn = min(kChunk, n - c0);
     int j = 0;
     while (j < cn) {
       // Common steps, far from every lane of the wave, up to the next step
-      // where some lane loads its state or the stroke comes near: every lane
-      // regenerates x_i = Phi_i(x_{i-1}) (Eq. rpos), and alpha, mu dalpha and
-      // the colour terms vanish to FP32. Phi moves a point away from the
-      // stroke, so a wave that is far before the step is far after it and
-      // the vote can come first. Keeping these steps in a loop of their own,
-      // with the general step after it, leaves the loop one path: the state
-      // it carries needs no register copies where paths would join. The
-      // record is read before the exit tests and handed to the general step:
-      // used on both sides of them, all its loads issue at the top of the
-      // step (loads used only after the far vote would issue after it, with
-      // their latency in the way).
+      // where some lane loads its state (a wave-uniform index: a scalar
+      // compare) or the stroke comes near: every lane regenerates x_i =
+      // Phi_i(x_{i-1}) (Eq. rpos), and alpha, mu dalpha and the colour terms
+      // vanish to FP32. Phi moves a point away from the stroke, so a wave
+      // that is far before the step is far after it and the vote can come
+      // first. Under uniform insertion the loop takes only waves whose lanes
+      // all lie on the stroke's cap (far_cap_step; about 95% of far steps
+      // here), and the rest go to the general step: the loop keeps one path,
+      // so the state it carries needs no register copies where paths would
+      // join, and the polar step's chain of reciprocals interleaves with its
+      // atan. The record is read before the exit tests and handed to the
+      // general step: used on both sides of them, all its loads issue at the
+      // top of the step (loads used only after the far vote would issue
+      // after it, with their latency in the way).
       StrokeRec g;
       for (; j < cn; ++j) {
         const int i = c0 + j;  // stroke index (0-based); its input state is x_{i+1}
         g = load_rec(recs, i);
-        if (i == next_ck || wave_any(top_idx == i)) break;
+        if (i == next_stop) break;
         Chart ca;
-        Leaf lf;
+        float v[5];
         if constexpr (kC) {  // the far vote needs the leaf's edge
           ca = chart(x, y, g);
-          lf = leaf_at<true>(ca, g, coup, i);
+          const Leaf lf = leaf_at<true>(ca, g, coup, i);
           if (!wave_all(is_far<true>(ca.sig, lf, g))) break;
+          Move mv = regenerate(ca, g, lf);
+          // unfolded displacement; psi runs from the regenerated x_i back to
+          // the chart point x_{i-1}, so its increments are Phi's negated
+          VjpIn vi;
+          vi.sgs = ca.sgs;
+          vi.sgh = ca.sgh;
+          vi.w = ca.w;
+          vi.floored = false;
+          vi.sig = mv.sig_o;
+          vi.th = mv.th_o;
+          vi.sn = mv.sn_o;
+          vi.cs = mv.cs_o;
+          vi.tf = mv.tf_o;
+          vi.inv_p1 = mv.inv_per_o;
+          vi.rho = ca.sig;
+          vi.inv_p0 = ca.inv_per;
+          vi.th_o = ca.th;
+          vi.sn_o = ca.sn;
+          vi.cs_o = ca.cs;
+          vi.tf_o = mv.tf;
+          vi.dsig = -mv.dsig;
+          vi.dth = -mv.dth;
+          vi.dsin = -mv.dsin;
+          vi.dcos = -mv.dcos;
+          vi.dtf = -mv.dtf;
+          vi.z = 0.f;
+          vi.alpha = 0.f;
+          vi.q = 1.f;
+          vi.clamped = true;
+          step_by(x, y, ca.sgs * mv.dS, ca.sgh * mv.dH, g);
+          const VjpOut vo = vjp_step<false, true>(vi, g, lx, ly, 0.f, lf);
+          lx = vo.gx;
+          ly = vo.gy;
+          v[0] = vo.nmx;
+          v[1] = vo.nmy;
+          v[2] = vo.gphi;
+          v[3] = vo.gell;
+          v[4] = vo.gr;
         } else {
-          lf = uniform_leaf(g);
+          // one vote: beyond the far margin and on the cap, for every lane
+          // (a wave with a lane on the flank takes the general step)
           chart_dist(x, y, g, ca);
-          if (!wave_all(is_far<false>(ca.sig, lf, g))) break;
-          chart_angle<true>(g, ca);
+          if (!wave_all2(ca.sig > g.far_sig, ca.E > 0.f)) break;
+          far_cap_step(x, y, lx, ly, ca, g, v);
         }
-        Move mv = regenerate(ca, g, lf);
-        // unfolded displacement; psi runs from the regenerated x_i back to
-        // the chart point x_{i-1}, so its increments are Phi's negated
-        const float da = ca.sgs * mv.dS, db = ca.sgh * mv.dH;
-        VjpIn vi;
-        vi.sgs = ca.sgs;
-        vi.sgh = ca.sgh;
-        vi.w = ca.w;
-        vi.floored = false;
-        vi.sig = mv.sig_o;
-        vi.th = mv.th_o;
-        vi.sn = mv.sn_o;
-        vi.cs = mv.cs_o;
-        vi.tf = mv.tf_o;
-        vi.inv_p1 = mv.inv_per_o;
-        vi.rho = ca.sig;
-        vi.inv_p0 = ca.inv_per;
-        vi.th_o = ca.th;
-        vi.sn_o = ca.sn;
-        vi.cs_o = ca.cs;
-        vi.tf_o = mv.tf;
-        vi.dsig = -mv.dsig;
-        vi.dth = -mv.dth;
-        vi.dsin = -mv.dsin;
-        vi.dcos = -mv.dcos;
-        vi.dtf = -mv.dtf;
-        vi.z = 0.f;
-        vi.alpha = 0.f;
-        vi.q = 1.f;
-        vi.clamped = true;
-        step_by(x, y, da, db, g);
-        VjpOut vo;
-        if constexpr (kC) {
-          vo = vjp_step<false, true>(vi, g, lx, ly, 0.f, lf);
-        } else if (mv.all_cap) {
-          vo = vjp_far<true>(vi, g, lx, ly);
-        } else {
-          vo = vjp_far<false>(vi, g, lx, ly);
-        }
-        lx = vo.gx;
-        ly = vo.gy;
-        float v[5] = {vo.nmx, vo.nmy, vo.gphi, vo.gell, vo.gr};
         const float tot = row_sums5(v, lane);
         if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
       }
@@ -795,7 +807,8 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
       {
         // The general step: the stroke is near some lane of the wave, or
         // some lane takes x_i from the side table (the floor bound there in
-        // the forward pass), or the step is a checkpoint (drift reset).
+        // the forward pass), or the step is a checkpoint (drift reset), or
+        // (uniform insertion) some lane of a far wave lies on the flank.
         const int i = c0 + j;
         const bool ck = i == next_ck;
         if (ck) next_ck = next_ck + k + 1 < n ? next_ck + k : 0x7fffffff;
@@ -808,6 +821,8 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           --top;
           top_idx = top > 0 ? tape.side_idx[(size_t)(top - 1) * P + id.p] : -1;
         }
+        if (i == next_pop) next_pop = wave_next_pop(top_idx);
+        next_stop = min(next_ck, next_pop);
         float2 ckt = make_float2(1.f, 0.f);
         if (ck && id.active) {
           double2 r = tape.ckpt_xy[(size_t)((i + 1) / k) * P + id.p];
