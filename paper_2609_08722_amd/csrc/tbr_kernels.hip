@@ -454,41 +454,40 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int n, int v) {
 // ---------------------------------------------------------------------------
 // Cross-lane reduction of 8 per-lane values to 16-lane row sums.
 // Three transpose stages halve the value set while exchanging with lane^1,
-// lane^2, lane^4 (DPP quad permutes and row shifts); lane^8 is a row
-// rotation by 8. Afterwards lanes l and l + 8 of each 16-lane row hold the
-// row's sum of value index bitrev3(l & 7). The four rows of a wave are added
-// later, in a fixed order, together with the block's other waves.
+// lane^2, lane^4; a last exchange with lane^8 adds the row's two halves.
+// Afterwards lanes l and l + 8 of each 16-lane row hold the row's sum of
+// value index bitrev3(l & 7). The four rows of a wave are added later, in a
+// fixed order, together with the block's other waves. The exchanges are
+// ds_swizzle xor patterns: they run on the LDS crossbar, and the adds that
+// follow are plain vector adds (a DPP add issues at about half the rate of
+// a plain one on gfx950).
 // ---------------------------------------------------------------------------
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+template <int kXor>
+__device__ __forceinline__ float swz_xor(float v) {
+  // bit mode: and_mask 0x1F, or_mask 0, xor_mask kXor (within 32 lanes)
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), (kXor << 10) | 0x1F));
 }
-constexpr int kQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
-constexpr int kQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
-constexpr int kRowShl4 = 0x104;
-constexpr int kRowShr4 = 0x114;
-constexpr int kRowRor8 = 0x128;
 
 __device__ __forceinline__ float row_sums8(const float (&v)[8], int lane) {
   const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
   float u[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    float r0 = v[j] + dpp_mov<kQuadXor1>(v[j]);
-    float r1 = v[j + 4] + dpp_mov<kQuadXor1>(v[j + 4]);
+    float r0 = v[j] + swz_xor<1>(v[j]);
+    float r1 = v[j + 4] + swz_xor<1>(v[j + 4]);
     u[j] = b0 ? r1 : r0;
   }
   float w[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    float r0 = u[j] + dpp_mov<kQuadXor2>(u[j]);
-    float r1 = u[j + 2] + dpp_mov<kQuadXor2>(u[j + 2]);
+    float r0 = u[j] + swz_xor<2>(u[j]);
+    float r1 = u[j + 2] + swz_xor<2>(u[j + 2]);
     w[j] = b1 ? r1 : r0;
   }
-  float r0 = w[0] + dpp_mov<kRowShl4>(w[0]);
-  float r1 = w[1] + dpp_mov<kRowShr4>(w[1]);
+  float r0 = w[0] + swz_xor<4>(w[0]);
+  float r1 = w[1] + swz_xor<4>(w[1]);
   float t = b2 ? r1 : r0;
-  return t + dpp_mov<kRowRor8>(t);
+  return t + swz_xor<8>(t);
 }
 
 // Same result when values 5..7 are zero (strokes far from the wave). The
@@ -499,23 +498,23 @@ __device__ __forceinline__ float row_sums5(const float (&v)[5], int lane) {
   const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
   float u[4];
   {
-    float r0 = v[0] + dpp_mov<kQuadXor1>(v[0]);
-    float r1 = v[4] + dpp_mov<kQuadXor1>(v[4]);
+    float r0 = v[0] + swz_xor<1>(v[0]);
+    float r1 = v[4] + swz_xor<1>(v[4]);
     u[0] = b0 ? r1 : r0;
   }
 #pragma unroll
-  for (int j = 1; j < 4; ++j) u[j] = v[j] + dpp_mov<kQuadXor1>(v[j]);
+  for (int j = 1; j < 4; ++j) u[j] = v[j] + swz_xor<1>(v[j]);
   float w[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    float r0 = u[j] + dpp_mov<kQuadXor2>(u[j]);
-    float r1 = u[j + 2] + dpp_mov<kQuadXor2>(u[j + 2]);
+    float r0 = u[j] + swz_xor<2>(u[j]);
+    float r1 = u[j + 2] + swz_xor<2>(u[j + 2]);
     w[j] = b1 ? r1 : r0;
   }
-  float r0 = w[0] + dpp_mov<kRowShl4>(w[0]);
-  float r1 = w[1] + dpp_mov<kRowShr4>(w[1]);
+  float r0 = w[0] + swz_xor<4>(w[0]);
+  float r1 = w[1] + swz_xor<4>(w[1]);
   float t = b2 ? r1 : r0;
-  t += dpp_mov<kRowRor8>(t);
+  t += swz_xor<8>(t);
   return (b0 && (b1 || b2)) ? 0.f : t;
 }
 
