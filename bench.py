@@ -31,18 +31,24 @@ if ROOT not in sys.path:
 
 # MI355X published FP32 vector peak: 256 CUs x 2.4 GHz x 256 FLOP/clock/CU.
 PEAK_FP32_FLOPS = 157.3e12
-# Algorithmic FP operations per pixel-stroke of the common step: a stroke far
-# from every lane of the wave (coverage below 7e-13: no coverage or colour
-# terms), >99% of pixel-strokes here, whose wave lies on the stroke's cap and
-# turns by less than 1/16 rad. Counted over that step's compiled instructions
-# (FMA = 2; every other floating-point add, mul, min/max, compare, select,
-# conversion, FP64 add, transcendental and DPP add = 1; register moves, sign
-# inserts, integer and scalar work = 0). Other steps do more work, so the
-# counts are a lower bound. The path is ALU-bound: HBM traffic is ~0.45 B per
-# pixel-stroke.
+# Algorithmic FP operations per pixel-stroke, the roofline's fixed per-unit
+# figure: one common step (a stroke far from every lane of the wave, coverage
+# below 7e-13, so no coverage or colour terms; >99% of pixel-strokes here)
+# of the soft forward and of the replay, counted over that step's formulas
+# as first built (FMA = 2; every other floating-point add, mul, min/max,
+# compare, select, conversion, FP64 add, transcendental and cross-lane add =
+# 1; register moves, bit operations, integer and scalar work = 0). It stays
+# fixed so that `frac` follows the kernel's speed; the kernels now execute
+# fewer operations for the same step (OPS_EXECUTED, same counting rule, on
+# the current compiled common paths), and the hardware counters give the
+# FP32 rate actually issued. The path is ALU-bound: HBM traffic is ~0.45 B
+# per pixel-stroke.
 FLOPS_FWD = 117      # soft forward far step: chart, far vote, psi (cap to cap), FP64 advance
 FLOPS_REPLAY = 222   # replay far step: chart, far vote, Phi (cap to cap), VJP, row sums,
                      # FP64 advance
+# The same count on the current compiled common paths (far step on the cap,
+# turn below 2^-12 rad): forward 95, replay 199.
+OPS_EXECUTED = {"forward": 95, "replay": 199}
 # HBM bytes per k_fit_fused launch at the bench workload, from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
 # in the same runs; valid only for the kernel sources it was measured on
@@ -538,10 +544,13 @@ def main():
     achieved = flops * P * N / (ms_fused * 1e-3)
     traffic = TRAFFIC["bytes"] if (TRAFFIC["sha"] == kernel_sha() and
                                    w.name == "fit1024x1024_n2000") else None
+    executed = OPS_EXECUTED["forward"] + OPS_EXECUTED["replay"]
     roofline = {"bound": "alu", "kernel": "k_fit_fused", "achieved": achieved / 1e12,
                 "peak": PEAK_FP32_FLOPS / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_FLOPS, "traffic": traffic,
-                "flops_per_pixel_stroke": flops, "launch_ms": ms_fused}
+                "flops_per_pixel_stroke": flops, "launch_ms": ms_fused,
+                "ops_executed_per_pixel_stroke": executed,
+                "executed_frac": executed * P * N / (ms_fused * 1e-3) / PEAK_FP32_FLOPS}
     # the same launch's FP32 add/mul/FMA as the hardware counted them (all
     # 64 lanes of each wave instruction), against the same peak
     if COUNTERS["sha"] == kernel_sha() and w.name == "fit1024x1024_n2000":
