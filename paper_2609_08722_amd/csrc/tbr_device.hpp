@@ -668,6 +668,30 @@ __device__ __forceinline__ void advance(double& x, double& y, const Chart& c, co
 template <bool kAngle>
 __device__ __forceinline__ void psi_far_advance(double& x, double& y, const Chart& c, float th,
                                                 const StrokeRec& g, const Leaf& lf) {
+  if constexpr (kAngle) {
+    // The chart's own sine, cosine and 1 / P_l(sig) serve the same step
+    // (fewer live values where the full chart exists anyway):
+    // dS = dsig (sin th + dsin) + sig dsin, dH likewise.
+    const float q = back_area(c.sig, lf, g.two_ell);
+    const Root rt = area_root(q, g);
+    const float dsig = -lf.ar * rcp(fmaf(kPi, c.sig, rt.d));
+    const float dth = dsig * g.ell * (kPi - 2.f * c.th) * (c.inv_per * rcp(rt.sig_o));
+    if (wave_all(c.th + dth > 0.f)) {
+      float sd, cdm1;
+      if (wave_all(fabsf(dth) < kSmallTurn)) {
+        sincosm1_small(dth, sd, cdm1);
+      } else {
+        sincosm1(dth, sd, cdm1);
+      }
+      const float dsin = fmaf(c.sn, cdm1, c.cs * sd);
+      const float dcos = fmaf(c.cs, cdm1, -(c.sn * sd));
+      step_by(x, y, c.sgs * fmaf(dsig, c.sn + dsin, c.sig * dsin),
+              c.sgh * fmaf(dsig, c.cs + dcos, c.sig * dcos), g);
+      return;
+    }
+    advance(x, y, c, displace<false, false>(c, g, true, lf), g);
+    return;
+  }
   const float q = fmaf(c.sig, fmaf(kPi, c.sig, g.two_ell), -lf.ar);
   const float D = g.ell + hw_sqrt(fmaf(g.ell, g.ell, kPi * q));
   const float k = -lf.ar * rcp(c.sig * fmaf(kPi, c.sig, D));
@@ -685,7 +709,7 @@ __device__ __forceinline__ void psi_far_advance(double& x, double& y, const Char
     return;
   }
   Chart cf = c;
-  if constexpr (!kAngle) chart_angle<true>(g, cf);
+  chart_angle<true>(g, cf);
   advance(x, y, cf, displace<false, false>(cf, g, true, lf), g);
 }
 

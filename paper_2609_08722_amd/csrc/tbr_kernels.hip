@@ -457,64 +457,100 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int n, int v) {
 // lane^2, lane^4; a last exchange with lane^8 adds the row's two halves.
 // Afterwards lanes l and l + 8 of each 16-lane row hold the row's sum of
 // value index bitrev3(l & 7). The four rows of a wave are added later, in a
-// fixed order, together with the block's other waves. The exchanges are
-// ds_swizzle xor patterns: they run on the LDS crossbar, and the adds that
-// follow are plain vector adds (a DPP add issues at about half the rate of
-// a plain one on gfx950).
+// fixed order, together with the block's other waves.
+//
+// Two ways to exchange, with the same pairwise sums (bitwise the same
+// results): DPP (quad permutes, row shifts by 4, a row rotation by 8), or
+// ds_swizzle xor patterns, which run on the LDS crossbar so that the adds
+// after them are plain vector adds (a DPP add issues at about half the rate
+// of a plain one on gfx950) but wait on the crossbar's latency. Measured
+// per map at 1024^2 x 2000: the capsule map's fit step (6 waves per SIMD)
+// is 1.4% faster with the swizzles, the coupled map's (5 waves) 12% slower,
+// so kSwz is set for the capsule map only.
 // ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+constexpr int kQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int kRowShl4 = 0x104;
+constexpr int kRowShr4 = 0x114;
+constexpr int kRowRor8 = 0x128;
+
 template <int kXor>
 __device__ __forceinline__ float swz_xor(float v) {
   // bit mode: and_mask 0x1F, or_mask 0, xor_mask kXor (within 32 lanes)
   return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), (kXor << 10) | 0x1F));
 }
 
+// The value of lane^1, lane^2, lane^8; and of lane^4 as seen from the lanes
+// with bit 2 clear (lo) or set (hi), the only lanes whose result is kept.
+template <bool kSwz> __device__ __forceinline__ float xch1(float v) {
+  if constexpr (kSwz) return swz_xor<1>(v); else return dpp_mov<kQuadXor1>(v);
+}
+template <bool kSwz> __device__ __forceinline__ float xch2(float v) {
+  if constexpr (kSwz) return swz_xor<2>(v); else return dpp_mov<kQuadXor2>(v);
+}
+template <bool kSwz> __device__ __forceinline__ float xch4lo(float v) {
+  if constexpr (kSwz) return swz_xor<4>(v); else return dpp_mov<kRowShl4>(v);
+}
+template <bool kSwz> __device__ __forceinline__ float xch4hi(float v) {
+  if constexpr (kSwz) return swz_xor<4>(v); else return dpp_mov<kRowShr4>(v);
+}
+template <bool kSwz> __device__ __forceinline__ float xch8(float v) {
+  if constexpr (kSwz) return swz_xor<8>(v); else return dpp_mov<kRowRor8>(v);
+}
+
+template <bool kSwz>
 __device__ __forceinline__ float row_sums8(const float (&v)[8], int lane) {
   const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
   float u[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    float r0 = v[j] + swz_xor<1>(v[j]);
-    float r1 = v[j + 4] + swz_xor<1>(v[j + 4]);
+    float r0 = v[j] + xch1<kSwz>(v[j]);
+    float r1 = v[j + 4] + xch1<kSwz>(v[j + 4]);
     u[j] = b0 ? r1 : r0;
   }
   float w[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    float r0 = u[j] + swz_xor<2>(u[j]);
-    float r1 = u[j + 2] + swz_xor<2>(u[j + 2]);
+    float r0 = u[j] + xch2<kSwz>(u[j]);
+    float r1 = u[j + 2] + xch2<kSwz>(u[j + 2]);
     w[j] = b1 ? r1 : r0;
   }
-  float r0 = w[0] + swz_xor<4>(w[0]);
-  float r1 = w[1] + swz_xor<4>(w[1]);
+  float r0 = w[0] + xch4lo<kSwz>(w[0]);
+  float r1 = w[1] + xch4hi<kSwz>(w[1]);
   float t = b2 ? r1 : r0;
-  return t + swz_xor<8>(t);
+  return t + xch8<kSwz>(t);
 }
 
 // Same result when values 5..7 are zero (strokes far from the wave). The
 // lanes that end with value index 4..7 (lane bit 0 set) only ever combine
 // with each other, so the stage-1 sums of values 1..3 may stand in for the
 // missing 5..7 there; one select zeroes the lanes of values 5..7 at the end.
+template <bool kSwz>
 __device__ __forceinline__ float row_sums5(const float (&v)[5], int lane) {
   const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
   float u[4];
   {
-    float r0 = v[0] + swz_xor<1>(v[0]);
-    float r1 = v[4] + swz_xor<1>(v[4]);
+    float r0 = v[0] + xch1<kSwz>(v[0]);
+    float r1 = v[4] + xch1<kSwz>(v[4]);
     u[0] = b0 ? r1 : r0;
   }
 #pragma unroll
-  for (int j = 1; j < 4; ++j) u[j] = v[j] + swz_xor<1>(v[j]);
+  for (int j = 1; j < 4; ++j) u[j] = v[j] + xch1<kSwz>(v[j]);
   float w[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    float r0 = u[j] + swz_xor<2>(u[j]);
-    float r1 = u[j + 2] + swz_xor<2>(u[j + 2]);
+    float r0 = u[j] + xch2<kSwz>(u[j]);
+    float r1 = u[j + 2] + xch2<kSwz>(u[j + 2]);
     w[j] = b1 ? r1 : r0;
   }
-  float r0 = w[0] + swz_xor<4>(w[0]);
-  float r1 = w[1] + swz_xor<4>(w[1]);
+  float r0 = w[0] + xch4lo<kSwz>(w[0]);
+  float r1 = w[1] + xch4hi<kSwz>(w[1]);
   float t = b2 ? r1 : r0;
-  t += swz_xor<8>(t);
+  t += xch8<kSwz>(t);
   return (b0 && (b1 || b2)) ? 0.f : t;
 }
 
@@ -582,7 +618,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
   {
     float t0 = trans_value(tm, te);
     float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, lcr * t0, lcg * t0, lcb * t0};
-    float tot = row_sums8(v, lane);
+    float tot = row_sums8<kT == kCapsule>(v, lane);
     __syncthreads();  // lds may still be read by a previous tile of this block
     if (!(lane & 8)) lds[0][wave * 4 + (lane >> 4)][0][value_index_of_lane(lane)] = tot;
     __syncthreads();
@@ -629,7 +665,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           lt = fmaf(cv.alpha, dlt, lt);  // (1 - alpha) lt + alpha lc
           VjpOut vo = vjp_cover_only(ca, g, cv, mu);
           float v[8] = {vo.nmx, vo.nmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
-          tot = row_sums8(v, lane);
+          tot = row_sums8<kT == kCapsule>(v, lane);
         }
         if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
       }
@@ -703,7 +739,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           v[6] = lcg * ta;
           v[7] = lcb * ta;
         }
-        const float tot = row_sums8(v, lane);
+        const float tot = row_sums8<kT == kCapsule>(v, lane);
         if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
       }
       __syncthreads();
@@ -720,8 +756,10 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
     return;
   }
   constexpr bool kC = kT == kCoupled;
-  // the next step that some lane of the wave loads (a checkpoint or a pop)
-  int next_pop = wave_next_pop(top_idx);
+  // the next step that some lane of the wave loads (a checkpoint or a pop);
+  // the coupled map votes on the lanes' own next pops instead (a wave
+  // minimum in its general step costs it registers)
+  int next_pop = kC ? 0x7fffffff : wave_next_pop(top_idx);
   int next_stop = min(next_ck, next_pop);
   for (int c0 = 0; c0 < n; c0 += kChunk) {
     const int buf = (c0 / kChunk) & 1;
@@ -747,7 +785,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
       for (; j < cn; ++j) {
         const int i = c0 + j;  // stroke index (0-based); its input state is x_{i+1}
         g = load_rec(recs, i);
-        if (i == next_stop) break;
+        if (kC ? (i == next_ck || wave_any(top_idx == i)) : i == next_stop) break;
         Chart ca;
         float v[5];
         if constexpr (kC) {  // the far vote needs the leaf's edge
@@ -757,6 +795,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           Move mv = regenerate(ca, g, lf);
           // unfolded displacement; psi runs from the regenerated x_i back to
           // the chart point x_{i-1}, so its increments are Phi's negated
+          const float da = ca.sgs * mv.dS, db = ca.sgh * mv.dH;
           VjpIn vi;
           vi.sgs = ca.sgs;
           vi.sgh = ca.sgh;
@@ -783,7 +822,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           vi.alpha = 0.f;
           vi.q = 1.f;
           vi.clamped = true;
-          step_by(x, y, ca.sgs * mv.dS, ca.sgh * mv.dH, g);
+          step_by(x, y, da, db, g);
           const VjpOut vo = vjp_step<false, true>(vi, g, lx, ly, 0.f, lf);
           lx = vo.gx;
           ly = vo.gy;
@@ -799,7 +838,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           if (!wave_all2(ca.sig > g.far_sig, ca.E > 0.f)) break;
           far_cap_step(x, y, lx, ly, ca, g, v);
         }
-        const float tot = row_sums5(v, lane);
+        const float tot = row_sums5<kT == kCapsule>(v, lane);
         if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
       }
       if (j == cn) break;
@@ -820,8 +859,10 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           --top;
           top_idx = top > 0 ? tape.side_idx[(size_t)(top - 1) * P + id.p] : -1;
         }
-        if (i == next_pop) next_pop = wave_next_pop(top_idx);
-        next_stop = min(next_ck, next_pop);
+        if constexpr (!kC) {
+          if (i == next_pop) next_pop = wave_next_pop(top_idx);
+          next_stop = min(next_ck, next_pop);
+        }
         float2 ckt = make_float2(1.f, 0.f);
         if (ck && id.active) {
           double2 r = tape.ckpt_xy[(size_t)((i + 1) / k) * P + id.p];
@@ -901,7 +942,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
         lx = vo.gx;
         ly = vo.gy;
         float v[8] = {vo.nmx, vo.nmy, vo.gphi, vo.gell, vo.gr, lcr * ta, lcg * ta, lcb * ta};
-        tot = row_sums8(v, lane);
+        tot = row_sums8<kT == kCapsule>(v, lane);
         if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
         ++j;
       }
