@@ -53,14 +53,14 @@ OPS_EXECUTED = {"forward": 95, "replay": 199}
 # FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
 # in the same runs; valid only for the kernel sources it was measured on
 # (or sources whose k_fit_fused<0> compiles to the same code).
-TRAFFIC = {"sha": "a903a2411b082d12", "bytes": 387.3e6 + 605.0e6}
+TRAFFIC = {"sha": "8411a931bba390a2", "bytes": 414.3e6 + 610.2e6}
 # Wave-level instruction counts per k_fit_fused<0> launch at the bench
 # workload (rocprofv3 --pmc, per-dispatch averages), for the same sources
 # only: SQ_INSTS_VALU_{FMA,ADD,MUL}_F32, SQ_INSTS_VALU_TRANS_F32 and
 # SQ_INSTS_VALU. Each wave instruction does 64 lane operations.
-COUNTERS = {"sha": "a903a2411b082d12",
-            "fma_f32": 2.9794e+09, "add_f32": 8.1538e+08, "mul_f32": 2.5776e+09,
-            "trans_f32": 5.2631e+08, "valu": 8.9245e+09}
+COUNTERS = {"sha": "8411a931bba390a2",
+            "fma_f32": 2.707e+09, "add_f32": 7.061e+08, "mul_f32": 2.362e+09,
+            "trans_f32": 3.523e+08, "valu": 7.748e+09}
 
 
 def kernel_sha():
