@@ -134,19 +134,27 @@ __device__ __forceinline__ void chart_dist(double x, double y, const StrokeRec& 
 }
 
 // The cap angle alone, for a point off the segment (sigma > 0): all that a
-// far step which stays on the cap needs of the chart's angle part.
+// far step which stays on the cap needs of the chart's angle part. By the
+// half-angle identity th = 2 atan(t) with t = tan(th / 2) = E / (sigma + H),
+// and t lies in [0, 1] for th in [0, pi/2], so unlike atan(E / H) the
+// argument needs no fold (no min / max, no select, no pi/2 - atan). The
+// polynomial for 2 atan is one degree longer than atan01's; in FP32 the
+// angle comes out within 3.6e-7 (RMS 7e-8), against 3.8e-7 (RMS 1.8e-7)
+// for the folded atan01 form.
+constexpr int kTwoAtanTerms = sizeof(kTwoAtan) / sizeof(kTwoAtan[0]);
 __device__ __forceinline__ float far_theta(const Chart& c) {
-  const float hi = fmaxf(c.E, c.H), lo = fminf(c.E, c.H);
-  const float t = atan01(lo * rcp(hi));
-  return c.E > c.H ? kHalfPi - t : t;
+  const float t = c.E * rcp(c.sig + c.H);
+  const float u = t * t;
+  float p = kTwoAtan[kTwoAtanTerms - 1];
+#pragma unroll
+  for (int j = kTwoAtanTerms - 2; j >= 0; --j) p = fmaf(p, u, kTwoAtan[j]);
+  return t * p;
 }
 
 template <bool kFar = false>
 __device__ __forceinline__ void chart_angle(const StrokeRec& g, Chart& c) {
   if constexpr (kFar) {
-    const float hi = fmaxf(c.E, c.H), lo = fminf(c.E, c.H);
-    const float t = atan01(lo * rcp(hi));
-    c.th = c.E > c.H ? kHalfPi - t : t;
+    c.th = far_theta(c);
     c.inv_sig = rcp(c.sig);
     c.sn = c.E * c.inv_sig;
     c.cs = c.H * c.inv_sig;

@@ -502,6 +502,57 @@ template <bool kSwz> __device__ __forceinline__ float xch8(float v) {
   if constexpr (kSwz) return swz_xor<8>(v); else return dpp_mov<kRowRor8>(v);
 }
 
+// One far step by the general map: Phi (Eq. rpos) of the charted point
+// x_{i-1} with regenerate, which also takes lanes on the stroke's flank, and
+// psi's VJP without the coverage terms (alpha, mu dalpha and the colour
+// terms vanish to FP32 beyond the far margin). The coupled map's common
+// step; under uniform insertion, the step of a far wave with a lane on the
+// flank, which the polar cap-to-cap step does not cover.
+template <bool kC>
+__device__ __forceinline__ void far_general_step(double& x, double& y, float& lx, float& ly,
+                                                 const Chart& ca, const StrokeRec& g,
+                                                 const Leaf& lf, float (&v)[5]) {
+  Move mv = regenerate(ca, g, lf);
+  // unfolded displacement; psi runs from the regenerated x_i back to
+  // the chart point x_{i-1}, so its increments are Phi's negated
+  const float da = ca.sgs * mv.dS, db = ca.sgh * mv.dH;
+  VjpIn vi;
+  vi.sgs = ca.sgs;
+  vi.sgh = ca.sgh;
+  vi.w = ca.w;
+  vi.floored = false;
+  vi.sig = mv.sig_o;
+  vi.th = mv.th_o;
+  vi.sn = mv.sn_o;
+  vi.cs = mv.cs_o;
+  vi.tf = mv.tf_o;
+  vi.inv_p1 = mv.inv_per_o;
+  vi.rho = ca.sig;
+  vi.inv_p0 = ca.inv_per;
+  vi.th_o = ca.th;
+  vi.sn_o = ca.sn;
+  vi.cs_o = ca.cs;
+  vi.tf_o = mv.tf;
+  vi.dsig = -mv.dsig;
+  vi.dth = -mv.dth;
+  vi.dsin = -mv.dsin;
+  vi.dcos = -mv.dcos;
+  vi.dtf = -mv.dtf;
+  vi.z = 0.f;
+  vi.alpha = 0.f;
+  vi.q = 1.f;
+  vi.clamped = true;
+  step_by(x, y, da, db, g);
+  const VjpOut vo = vjp_step<false, kC>(vi, g, lx, ly, 0.f, lf);
+  lx = vo.gx;
+  ly = vo.gy;
+  v[0] = vo.nmx;
+  v[1] = vo.nmy;
+  v[2] = vo.gphi;
+  v[3] = vo.gell;
+  v[4] = vo.gr;
+}
+
 template <bool kSwz>
 __device__ __forceinline__ float row_sums8(const float (&v)[8], int lane) {
   const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
@@ -774,7 +825,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
       // that is far before the step is far after it and the vote can come
       // first. Under uniform insertion the loop takes only waves whose lanes
       // all lie on the stroke's cap (far_cap_step; about 95% of far steps
-      // here), and the rest go to the general step: the loop keeps one path,
+      // here), and the rest leave it for one step: the loop keeps one path,
       // so the state it carries needs no register copies where paths would
       // join, and the polar step's chain of reciprocals interleaves with its
       // atan. The record is read before the exit tests and handed to the
@@ -792,48 +843,10 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           ca = chart(x, y, g);
           const Leaf lf = leaf_at<true>(ca, g, coup, i);
           if (!wave_all(is_far<true>(ca.sig, lf, g))) break;
-          Move mv = regenerate(ca, g, lf);
-          // unfolded displacement; psi runs from the regenerated x_i back to
-          // the chart point x_{i-1}, so its increments are Phi's negated
-          const float da = ca.sgs * mv.dS, db = ca.sgh * mv.dH;
-          VjpIn vi;
-          vi.sgs = ca.sgs;
-          vi.sgh = ca.sgh;
-          vi.w = ca.w;
-          vi.floored = false;
-          vi.sig = mv.sig_o;
-          vi.th = mv.th_o;
-          vi.sn = mv.sn_o;
-          vi.cs = mv.cs_o;
-          vi.tf = mv.tf_o;
-          vi.inv_p1 = mv.inv_per_o;
-          vi.rho = ca.sig;
-          vi.inv_p0 = ca.inv_per;
-          vi.th_o = ca.th;
-          vi.sn_o = ca.sn;
-          vi.cs_o = ca.cs;
-          vi.tf_o = mv.tf;
-          vi.dsig = -mv.dsig;
-          vi.dth = -mv.dth;
-          vi.dsin = -mv.dsin;
-          vi.dcos = -mv.dcos;
-          vi.dtf = -mv.dtf;
-          vi.z = 0.f;
-          vi.alpha = 0.f;
-          vi.q = 1.f;
-          vi.clamped = true;
-          step_by(x, y, da, db, g);
-          const VjpOut vo = vjp_step<false, true>(vi, g, lx, ly, 0.f, lf);
-          lx = vo.gx;
-          ly = vo.gy;
-          v[0] = vo.nmx;
-          v[1] = vo.nmy;
-          v[2] = vo.gphi;
-          v[3] = vo.gell;
-          v[4] = vo.gr;
+          far_general_step<true>(x, y, lx, ly, ca, g, lf, v);
         } else {
           // one vote: beyond the far margin and on the cap, for every lane
-          // (a wave with a lane on the flank takes the general step)
+          // (a far wave with a lane on the flank leaves for far_general_step)
           chart_dist(x, y, g, ca);
           if (!wave_all2(ca.sig > g.far_sig, ca.E > 0.f)) break;
           far_cap_step(x, y, lx, ly, ca, g, v);
@@ -842,11 +855,28 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
         if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
       }
       if (j == cn) break;
+      if constexpr (!kC) {
+        // A far wave with a lane on the stroke's flank (about 5% of the
+        // steps here, 0.6% being near): the general map's far step, without
+        // the general step's coverage, transmittance and colour terms.
+        if (c0 + j != next_stop) {
+          Chart ca;
+          chart_dist(x, y, g, ca);
+          if (wave_all(ca.sig > g.far_sig)) {
+            chart_angle<true>(g, ca);
+            float v[5];
+            far_general_step<false>(x, y, lx, ly, ca, g, uniform_leaf(g), v);
+            const float tot = row_sums5<true>(v, lane);
+            if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
+            ++j;
+            continue;
+          }
+        }
+      }
       {
         // The general step: the stroke is near some lane of the wave, or
         // some lane takes x_i from the side table (the floor bound there in
-        // the forward pass), or the step is a checkpoint (drift reset), or
-        // (uniform insertion) some lane of a far wave lies on the flank.
+        // the forward pass), or the step is a checkpoint (drift reset).
         const int i = c0 + j;
         const bool ck = i == next_ck;
         if (ck) next_ck = next_ck + k + 1 < n ? next_ck + k : 0x7fffffff;
