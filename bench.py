@@ -47,8 +47,8 @@ FLOPS_FWD = 117      # soft forward far step: chart, far vote, psi (cap to cap),
 FLOPS_REPLAY = 222   # replay far step: chart, far vote, Phi (cap to cap), VJP, row sums,
                      # FP64 advance
 # The same count on the current compiled common paths (far step on the cap,
-# turn below 2^-12 rad): forward 95, replay 199.
-OPS_EXECUTED = {"forward": 95, "replay": 199}
+# turn below 2^-12 rad): forward 92, replay 196.
+OPS_EXECUTED = {"forward": 92, "replay": 196}
 # HBM bytes per k_fit_fused launch at the bench workload, from rocprofv3 --pmc
 # FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
 # in the same runs; valid only for the kernel sources it was measured on
@@ -66,7 +66,8 @@ COUNTERS = {"sha": "8411a931bba390a2",
 def kernel_sha():
     import hashlib
     h = hashlib.sha256()
-    for f in ("tbr_kernels.hip", "tbr_device.hpp", "tbr_kernels.hpp", "tbr_api.hip"):
+    for f in ("tbr_kernels.hip", "tbr_device.hpp", "tbr_kernels.hpp", "tbr_api.hip",
+              "minimax_coeffs.h"):
         with open(os.path.join(ROOT, "paper_2609_08722_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
