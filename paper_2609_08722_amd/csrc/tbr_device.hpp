@@ -77,23 +77,21 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 __device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float hw_exp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
 
-// atan(a) for a in [0, 1] (Horner's rule in a^2).
-constexpr int kAtanTerms = sizeof(kAtan) / sizeof(kAtan[0]);
-__device__ __forceinline__ float atan01(float a) {
-  const float u = a * a;
-  float p = kAtan[kAtanTerms - 1];
+// The cap angle of a point from its folded offset (E, H) from the cap's
+// centre, by the half-angle identity th = 2 atan(t), t = tan(th / 2) =
+// E / (sigma + H) (sh = sigma + H). For th in [0, pi/2] the argument lies in
+// [0, 1], so unlike atan(E / H) it needs no fold into [0, 1] (no min / max,
+// select or pi/2 - atan). The polynomial for 2 atan (Horner's rule in t^2)
+// gives the angle within 3.6e-7 in FP32 (RMS 7e-8), against 3.8e-7 (RMS
+// 1.8e-7) for the folded atan(min / max) form of one degree less.
+constexpr int kTwoAtanTerms = sizeof(kTwoAtan) / sizeof(kTwoAtan[0]);
+__device__ __forceinline__ float cap_angle(float E, float sh) {
+  const float t = E * rcp(sh);
+  const float u = t * t;
+  float p = kTwoAtan[kTwoAtanTerms - 1];
 #pragma unroll
-  for (int j = kAtanTerms - 2; j >= 0; --j) p = fmaf(p, u, kAtan[j]);
-  return a * p;
-}
-
-// atan2(y, x) for y, x >= 0 (first quadrant); 0 at the origin.
-__device__ __forceinline__ float atan2_q1(float y, float x) {
-  float hi = fmaxf(x, y), lo = fminf(x, y);
-  // at the origin lo = 0, so the floored reciprocal gives a = 0
-  float a = lo * rcp(fmaxf(hi, kMinNormal));
-  float t = atan01(a);
-  return y > x ? kHalfPi - t : t;
+  for (int j = kTwoAtanTerms - 2; j >= 0; --j) p = fmaf(p, u, kTwoAtan[j]);
+  return t * p;
 }
 
 // Chart of a point w.r.t. one stroke: local coordinates, distance to the
@@ -134,22 +132,8 @@ __device__ __forceinline__ void chart_dist(double x, double y, const StrokeRec& 
 }
 
 // The cap angle alone, for a point off the segment (sigma > 0): all that a
-// far step which stays on the cap needs of the chart's angle part. By the
-// half-angle identity th = 2 atan(t) with t = tan(th / 2) = E / (sigma + H),
-// and t lies in [0, 1] for th in [0, pi/2], so unlike atan(E / H) the
-// argument needs no fold (no min / max, no select, no pi/2 - atan). The
-// polynomial for 2 atan is one degree longer than atan01's; in FP32 the
-// angle comes out within 3.6e-7 (RMS 7e-8), against 3.8e-7 (RMS 1.8e-7)
-// for the folded atan01 form.
-constexpr int kTwoAtanTerms = sizeof(kTwoAtan) / sizeof(kTwoAtan[0]);
-__device__ __forceinline__ float far_theta(const Chart& c) {
-  const float t = c.E * rcp(c.sig + c.H);
-  const float u = t * t;
-  float p = kTwoAtan[kTwoAtanTerms - 1];
-#pragma unroll
-  for (int j = kTwoAtanTerms - 2; j >= 0; --j) p = fmaf(p, u, kTwoAtan[j]);
-  return t * p;
-}
+// far step which stays on the cap needs of the chart's angle part.
+__device__ __forceinline__ float far_theta(const Chart& c) { return cap_angle(c.E, c.sig + c.H); }
 
 template <bool kFar = false>
 __device__ __forceinline__ void chart_angle(const StrokeRec& g, Chart& c) {
@@ -161,8 +145,9 @@ __device__ __forceinline__ void chart_angle(const StrokeRec& g, Chart& c) {
     c.per = fmaf(kTwoPi, c.sig, g.two_ell);
     c.inv_per = rcp(c.per);
   } else {
-    c.th = atan2_q1(c.E, c.H);
-    // on the segment E = 0, so the floored reciprocal gives sin th = 0
+    // on the segment E = sigma = H = 0, so the floored reciprocals give
+    // th = 0 and sin th = 0
+    c.th = cap_angle(c.E, fmaxf(c.sig + c.H, kMinNormal));
     c.inv_sig = rcp(fmaxf(c.sig, kMinNormal));
     c.sn = c.E * c.inv_sig;
     c.cs = c.sig > 0.f ? c.H * c.inv_sig : 1.f;
@@ -705,9 +690,9 @@ __device__ __forceinline__ void psi_far_advance(double& x, double& y, const Char
   const float k = -lf.ar * rcp(c.sig * fmaf(kPi, c.sig, D));
   const float per = fmaf(kTwoPi, c.sig, g.two_ell);
   const float dth = (k * g.ell) * fmaf(-2.f, th, kPi) * rcp(per * (1.f + k));
-  if (wave_all(th + dth > 0.f)) {
+  if (__builtin_expect(wave_all(th + dth > 0.f), 1)) {
     float ra, rb;
-    if (wave_all(fabsf(dth) < kTinyTurn)) {
+    if (__builtin_expect(wave_all(fabsf(dth) < kTinyTurn), 1)) {
       turn_increment<true>(dth, c.E, c.H, ra, rb);
     } else {
       turn_increment<false>(dth, c.E, c.H, ra, rb);
@@ -969,7 +954,7 @@ __device__ __forceinline__ void far_cap_step(double& x, double& y, float& lx, fl
   const float kap = Ath * inv_Pa;  // 2 pi w - th_a
   const float dth = Ath * k * R;   // th_b - th_a = dsig kap_a / sig_b
   float ra, rb;                    // (R(dth) - I) (E, H)
-  if (wave_all(fabsf(dth) < kTinyTurn)) {
+  if (__builtin_expect(wave_all(fabsf(dth) < kTinyTurn), 1)) {
     turn_increment<true>(dth, a.E, a.H, ra, rb);
   } else {
     turn_increment<false>(dth, a.E, a.H, ra, rb);

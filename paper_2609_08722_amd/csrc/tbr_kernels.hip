@@ -235,7 +235,7 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
     bool near = false;
     for (; i >= 0; --i) {
       g = load_rec(recs, i);
-      if (kTape && i == next_ck) {
+      if (__builtin_expect(kTape && i == next_ck, 0)) {
         if (write_tape) {
           size_t o = (size_t)((i + 1) / k) * P + id.p;
           tape.ckpt_xy[o] = make_double2(x, y);
@@ -253,7 +253,7 @@ __device__ __forceinline__ SoftOut soft_pixel(const StrokeRec* __restrict__ recs
       } else {
         lf = uniform_leaf(g);
         chart_dist(x, y, g, c);
-        if (!wave_all(is_far<false>(c.sig, lf, g))) {
+        if (__builtin_expect(!wave_all(is_far<false>(c.sig, lf, g)), 0)) {
           chart_angle(g, c);
           near = true;
           break;
@@ -301,7 +301,7 @@ __device__ __forceinline__ void hard_pixel(const StrokeRec* __restrict__ recs,
   own = -1;
   lab = 0;
   for (int i = n - 1; i >= 0; --i) {
-    if (wave_all(done)) break;
+    if (__builtin_expect(wave_all(done), 0)) break;
     const StrokeRec g = load_rec(recs, i);
     if (!done) {
       Chart c;
@@ -316,7 +316,7 @@ __device__ __forceinline__ void hard_pixel(const StrokeRec* __restrict__ recs,
       if constexpr (kT == kCapsule || kT == kCoupled) {
         // Every lane still tracing lies beyond the stroke's far margin: none
         // can hit it, and psi's floor cannot bind there.
-        if (wave_all(is_far<kT == kCoupled>(c.sig, lf, g))) {
+        if (__builtin_expect(wave_all(is_far<kT == kCoupled>(c.sig, lf, g)), 1)) {
           psi_far_advance<kT == kCoupled>(x, y, c, kT == kCoupled ? c.th : far_theta(c), g, lf);
           continue;
         }
@@ -836,7 +836,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
       for (; j < cn; ++j) {
         const int i = c0 + j;  // stroke index (0-based); its input state is x_{i+1}
         g = load_rec(recs, i);
-        if (kC ? (i == next_ck || wave_any(top_idx == i)) : i == next_stop) break;
+        if (__builtin_expect(kC ? (i == next_ck || wave_any(top_idx == i)) : i == next_stop, 0)) break;
         Chart ca;
         float v[5];
         if constexpr (kC) {  // the far vote needs the leaf's edge
@@ -848,7 +848,7 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
           // one vote: beyond the far margin and on the cap, for every lane
           // (a far wave with a lane on the flank leaves for far_general_step)
           chart_dist(x, y, g, ca);
-          if (!wave_all2(ca.sig > g.far_sig, ca.E > 0.f)) break;
+          if (__builtin_expect(!wave_all2(ca.sig > g.far_sig, ca.E > 0.f), 0)) break;
           far_cap_step(x, y, lx, ly, ca, g, v);
         }
         const float tot = row_sums5<kT == kCapsule>(v, lane);
