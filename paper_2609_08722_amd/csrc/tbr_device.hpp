@@ -656,8 +656,10 @@ __device__ __forceinline__ void advance(double& x, double& y, const Chart& c, co
 // and with the folded offset p = (E, H) from the cap's centre the
 // displacement is k (p + r) + r, r = (R(dth) - I) p: no 1 / sigma, no sine
 // and cosine of th. Beyond the margin q = A_l(sig) - A has no cancellation
-// (sig - r >= 28 wd), so it is formed unfactored. A wave with a lane that
-// reaches the flank takes the general map.
+// (sig - r >= 28 wd), so it is formed unfactored. A wave whose lanes all
+// lie on the flank takes the flank's own step (S scaled by P_l(sig_o) /
+// P_l(sig), H moved by dsig), and any other wave with a lane that reaches
+// the flank takes the general map.
 template <bool kAngle>
 __device__ __forceinline__ void psi_far_advance(double& x, double& y, const Chart& c, float th,
                                                 const StrokeRec& g, const Leaf& lf) {
@@ -699,6 +701,14 @@ __device__ __forceinline__ void psi_far_advance(double& x, double& y, const Char
     }
     const float dS = fmaf(k, c.E + ra, ra), dH = fmaf(k, c.H + rb, rb);
     step_by(x, y, c.sgs * dS, c.sgh * dH, g);
+    return;
+  }
+  if (__builtin_expect(wave_all(c.E == 0.f), 1)) {
+    // every lane on the flank, where sigma = H and t = S: psi moves the
+    // point towards the segment by dsig and scales S by P_l(sig_o) /
+    // P_l(sig) <= 1 (fixed w), so it stays on the flank
+    const float dsig = k * c.sig;
+    step_by(x, y, c.sgs * (c.S * ((kTwoPi * dsig) * rcp(per))), c.sgh * dsig, g);
     return;
   }
   Chart cf = c;
@@ -989,6 +999,67 @@ __device__ __forceinline__ void far_cap_step(double& x, double& y, float& lx, fl
   // 2 w - 1/2 = (th_a + kap_a) / pi - 1/2
   v[3] = fmaf(-0.5f, de, fmaf(-dtan, fmaf(th + kap, kInvPi, -0.5f), 2.f * cb * (dsig - g.r)));
   v[4] = -(cb * g.per_r);
+}
+
+// Phi and psi's VJP for a wave whose lanes all lie on the stroke's flank
+// (E = 0) beyond its far margin and stay there: about 70% of the far waves
+// that are not all on the cap. On the flank sigma = H and the arclength
+// from the flank midpoint is t = S, so Phi (Eq. fwd), keeping the fraction
+// w = S / P_l(sigma), moves the point away from the segment by dsig and
+// scales S by P_b / P_a: the folded displacement is (S u, dsig) with
+// u = (P_b - P_a) / P_a. psi's Jacobian at b is triangular (S_a depends on
+// S_b and sigma_b, sigma_a on sigma_b alone), and with v = (P_b - P_a) / P_b
+// its VJP (Eq. adjstep) takes the folded lambda_a = (lS, lH) to lambda_b:
+//   lS_b - lS = -v lS,
+//   lH_b - lH = u lH + 2 pi S u (1 / P_b + 1 / P_a) lS.
+// With cb = (lH + 2 pi w lS) / P_a, the adjoint of the inserted area, the
+// stroke's contributions (Eq. adjparam) are
+//   centre  lambda_a - lambda_b (translation invariance; returned negated),
+//   r       -cb P_l(r),
+//   l       2 cb (dsig - r) + 2 v w lS (the area root, and S_a = w P_l(sig_a)
+//           with P_l growing by 2 per unit of l),
+//   phi     rotation invariance about m: the change of the cross product of
+//           the offset from m with the adjoint, (a - m) x lambda_a -
+//           (b - m) x lambda_b, which folded is
+//           -sgs sgh (S dlH + dS lH_b - H dlS - dsig lS_b).
+// Every difference between the two points is again a product of
+// increments. Returns false, with nothing changed, unless every lane stays on
+// the flank (S + S u <= l/2; a lane on the cap has S > l/2 and fails too).
+__device__ __forceinline__ bool far_flank_step(double& x, double& y, float& lx, float& ly,
+                                               const Chart& a, const StrokeRec& g,
+                                               float (&v)[5]) {
+  constexpr float kInvPi = 0.318309886183790671538f;
+  const float q = fmaf(a.sig, fmaf(kPi, a.sig, g.two_ell), g.ar);
+  const float X = fmaf(g.ell, g.ell, kPi * q);
+  const float rs = __builtin_amdgcn_rsqf(X);  // 2 / P_l(sig_b)
+  // 2 l + pi (sig_a + sig_b) = pi sig_a + l + sqrt(l^2 + pi q)
+  const float dsig = g.ar * rcp(fmaf(kPi, a.sig, fmaf(X, rs, g.ell)));
+  const float inv_Pa = rcp(fmaf(kTwoPi, a.sig, g.two_ell));
+  const float hdp = kPi * dsig;        // (P_b - P_a) / 2
+  const float u = 2.f * hdp * inv_Pa;  // (P_b - P_a) / P_a
+  const float dS = a.S * u;
+  if (__builtin_expect(!wave_all(a.S + dS <= g.hl), 0)) return false;
+  const float vb = hdp * rs;  // (P_b - P_a) / P_b
+  step_by(x, y, a.sgs * dS, a.sgh * dsig, g);
+  const float ge = fmaf(lx, g.ce, ly * g.se);
+  const float gn = fmaf(ly, g.ce, -(lx * g.se));
+  const float lS = a.sgs * ge, lH = a.sgh * gn;
+  const float dlS = -vb * lS;
+  const float dlH = fmaf(u, lH, (dS * fmaf(kPi, rs, kTwoPi * inv_Pa)) * lS);
+  const float ssd = a.sgs * dlS, shd = a.sgh * dlH;
+  const float dx = fmaf(ssd, g.ce, -(shd * g.se));
+  const float dy = fmaf(ssd, g.se, shd * g.ce);
+  lx += dx;
+  ly += dy;
+  const float w2 = (kTwoPi * a.S) * inv_Pa;  // 2 pi w
+  const float cb = fmaf(w2, lS, lH) * inv_Pa;
+  v[0] = dx;
+  v[1] = dy;
+  v[2] = -(a.sgs * a.sgh) *
+         (fmaf(a.S, dlH, dS * (lH + dlH)) - fmaf(a.H, dlS, dsig * (lS + dlS)));
+  v[3] = fmaf(2.f * cb, dsig - g.r, ((vb * kInvPi) * w2) * lS);
+  v[4] = -(cb * g.per_r);
+  return true;
 }
 
 }  // namespace tbr

@@ -857,15 +857,19 @@ __device__ __forceinline__ void replay_tile(const StrokeRec* __restrict__ recs,
       if (j == cn) break;
       if constexpr (!kC) {
         // A far wave with a lane on the stroke's flank (about 5% of the
-        // steps here, 0.6% being near): the general map's far step, without
-        // the general step's coverage, transmittance and colour terms.
+        // steps here, 0.6% being near): the flank-to-flank step when every
+        // lane stays on the flank (about 3.5%), else the general map's far
+        // step, without the general step's coverage, transmittance and
+        // colour terms.
         if (c0 + j != next_stop) {
           Chart ca;
           chart_dist(x, y, g, ca);
           if (wave_all(ca.sig > g.far_sig)) {
-            chart_angle<true>(g, ca);
             float v[5];
-            far_general_step<false>(x, y, lx, ly, ca, g, uniform_leaf(g), v);
+            if (!far_flank_step(x, y, lx, ly, ca, g, v)) {  // flank to flank, or
+              chart_angle<true>(g, ca);
+              far_general_step<false>(x, y, lx, ly, ca, g, uniform_leaf(g), v);
+            }
             const float tot = row_sums5<true>(v, lane);
             if (!(lane & 8)) lds[buf][wave * 4 + (lane >> 4)][j][value_index_of_lane(lane)] = tot;
             ++j;
