@@ -1024,12 +1024,14 @@ __global__ void __launch_bounds__(256)
 // The forward and the replay share one register allocation here, so the
 // launch bound (waves per SIMD) trades registers for occupancy per
 // transport, as measured at 1024^2 x 2000 (bitwise the same results at
-// every bound): the capsule map at 6 waves (80 VGPRs; the few spills are of
-// values that live across a tile or a 16-stroke chunk) runs 7% faster than
-// at 5 (92 VGPRs, no spill) and 3% faster than at 7; the coupled map, with
+// every bound): the capsule map at 7 waves (72 VGPRs; its spills are of
+// values that live across a tile or a 16-stroke chunk, and one reload in
+// the forward's checkpoint store) runs 1.6-1.9% faster than at 6 (80
+// VGPRs), 4-5% faster than at 4 or 5 (98 / 96 VGPRs, no spill) and 5% faster
+// than at 8 (64 VGPRs, spills in the stroke loops); the coupled map, with
 // more live values, is fastest at 5; R_D at 7 (72 VGPRs).
 template <int kT>
-constexpr int kFusedWaves = kT == kCoupled ? 5 : (kT == kDrops ? 7 : 6);
+constexpr int kFusedWaves = kT == kCoupled ? 5 : 7;
 
 template <int kT>
 __global__ void __launch_bounds__(256, kFusedWaves<kT>) k_fit_fused(FitJobsK jobs,
