@@ -248,7 +248,10 @@ tbr_status launch_reduce(const tbr_program* p, const tbr_render_opts* o, const t
 
 // The fused fit kernel over the jobs' (job, tile) items; the cursor is
 // cleared by a fill kernel (no memset node if the caller captures a graph).
-tbr_status launch_fused(const FitJobsK& K, int* cursor, int transport, hipStream_t st) {
+// long_strokes selects the capsule map's 6-wave instantiation (programs
+// whose strokes may be long; see kFusedWavesLong).
+tbr_status launch_fused(const FitJobsK& K, int* cursor, int transport, bool long_strokes,
+                        hipStream_t st) {
   k_fill_i32<<<1, 64, 0, st>>>(cursor, 1, 0);
   tbr_status s = check_launch("fill");
   if (s) return s;
@@ -256,10 +259,17 @@ tbr_status launch_fused(const FitJobsK& K, int* cursor, int transport, hipStream
     Timed tm("fit_fused", st);
     const int grid = std::min(K.n_items, 256 * 8);
     switch (transport) {
-      case kCoupled: k_fit_fused<kCoupled><<<grid, 256, 0, st>>>(K, cursor); break;
-      case kInert: k_fit_fused<kInert><<<grid, 256, 0, st>>>(K, cursor); break;
-      case kDrops: k_fit_fused<kDrops><<<grid, 256, 0, st>>>(K, cursor); break;
-      default: k_fit_fused<kCapsule><<<grid, 256, 0, st>>>(K, cursor); break;
+      case kCoupled:
+        k_fit_fused<kCoupled, kFusedWaves<kCoupled>><<<grid, 256, 0, st>>>(K, cursor);
+        break;
+      case kInert: k_fit_fused<kInert, kFusedWaves<kInert>><<<grid, 256, 0, st>>>(K, cursor); break;
+      case kDrops: k_fit_fused<kDrops, kFusedWaves<kDrops>><<<grid, 256, 0, st>>>(K, cursor); break;
+      default:
+        if (long_strokes)
+          k_fit_fused<kCapsule, kFusedWavesLong><<<grid, 256, 0, st>>>(K, cursor);
+        else
+          k_fit_fused<kCapsule, kFusedWaves<kCapsule>><<<grid, 256, 0, st>>>(K, cursor);
+        break;
     }
   }
   return check_launch("fit_fused");
@@ -348,7 +358,7 @@ size_t multi_offset(const tbr_fit_job* jobs, int j) {
 tbr_status fit_core(int32_t n_strokes, int32_t n_palette, float* params, float* grads,
                     const tbr_render_opts* opts, const float* target_rgb, float* loss,
                     void* workspace, size_t workspace_bytes, hipStream_t st, float** g_out,
-                    const int32_t** records) {
+                    const int32_t** records, bool long_strokes = false) {
   tbr_status s;
   if (n_strokes < 0 || n_palette < 1 || n_palette > 64)
     return fail(TBR_E_INVALID, "n_strokes %d / n_palette %d out of range", n_strokes, n_palette);
@@ -411,7 +421,8 @@ tbr_status fit_core(int32_t n_strokes, int32_t n_palette, float* params, float* 
   D.tiles_x = tiles_x(opts);
   D.item0 = 0;
   KJ.n_items = (int)n_tiles(opts);
-  if ((s = launch_fused(KJ, reinterpret_cast<int*>(ws + FL.cursor), opts->transport, st)))
+  if ((s = launch_fused(KJ, reinterpret_cast<int*>(ws + FL.cursor), opts->transport,
+                        long_strokes, st)))
     return s;
   k_loss_final<<<1, 256, 0, st>>>(lpart, (int)n_tiles(opts), 1.0f / (3.0f * (float)n_pixels(opts)),
                                   loss);
@@ -651,6 +662,10 @@ tbr_status tbr_window_map(int32_t n_strokes, int32_t n_palette, const float* the
   return check_launch("window_map");
 }
 
+// A window whose offset bound per component exceeds this (canvas units)
+// admits long strokes: the fused launch then takes kFusedWavesLong.
+constexpr float kLongOffset = 0.1f;
+
 tbr_status tbr_fit_loop_step(int32_t n_strokes, int32_t n_palette, float* theta, float* params,
                              float* grads, float* adam_m, float* adam_v,
                              const tbr_window_opts* window, const tbr_adam_opts* adam,
@@ -676,8 +691,9 @@ tbr_status tbr_fit_loop_step(int32_t n_strokes, int32_t n_palette, float* theta,
   if ((s = tbr_window_map(N, K, theta, params, window, stream))) return s;
   float* g = nullptr;
   const int32_t* records = nullptr;
+  // offsets beyond a tenth of the canvas per component allow long strokes
   if ((s = fit_core(N, K, params, grads, opts, target_rgb, loss, workspace, workspace_bytes, st,
-                    &g, &records)))
+                    &g, &records, window->l_max > kLongOffset)))
     return s;
   k_reg_loss<<<1, 256, 0, st>>>(params, N, w, loss);
   if ((s = check_launch("reg_loss"))) return s;
@@ -847,7 +863,8 @@ tbr_status tbr_fit_multi_step(const tbr_fit_job* jobs, int32_t n_jobs, void* wor
     items += (int)n_tiles(&J.opts);
   }
   K.n_items = items;
-  if ((s = launch_fused(K, reinterpret_cast<int*>(ws), jobs[0].opts.transport, st))) return s;
+  if ((s = launch_fused(K, reinterpret_cast<int*>(ws), jobs[0].opts.transport, false, st)))
+    return s;
   for (int j = 0; j < n_jobs; ++j) {
     const tbr_fit_job& J = jobs[j];
     const FitLayout& FL = layouts[j];

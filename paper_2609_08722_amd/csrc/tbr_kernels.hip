@@ -1021,21 +1021,10 @@ __global__ void __launch_bounds__(256)
 // tile (each lane reads back only its own tape). Partial rows are indexed by
 // tile, so the order in which blocks take tiles cannot change any sum.
 // ---------------------------------------------------------------------------
-// The forward and the replay share one register allocation here, so the
-// launch bound (waves per SIMD) trades registers for occupancy per
-// transport, as measured at 1024^2 x 2000 (bitwise the same results at
-// every bound): the capsule map at 7 waves (72 VGPRs; its spills are of
-// values that live across a tile or a 16-stroke chunk, and one reload in
-// the forward's checkpoint store) runs 1.6-1.9% faster than at 6 (80
-// VGPRs), 4-5% faster than at 4 or 5 (98 / 96 VGPRs, no spill) and 5% faster
-// than at 8 (64 VGPRs, spills in the stroke loops); the coupled map, with
-// more live values, is fastest at 5; R_D at 7 (72 VGPRs).
-template <int kT>
-constexpr int kFusedWaves = kT == kCoupled ? 5 : 7;
-
-template <int kT>
-__global__ void __launch_bounds__(256, kFusedWaves<kT>) k_fit_fused(FitJobsK jobs,
-                                                                   int* __restrict__ cursor) {
+// The launch bound kW: kFusedWaves<kT>, or kFusedWavesLong for programs of
+// long strokes (tbr_kernels.hpp gives the measurements).
+template <int kT, int kW>
+__global__ void __launch_bounds__(256, kW) k_fit_fused(FitJobsK jobs, int* __restrict__ cursor) {
   __shared__ ReduceLds lds;
   __shared__ float red[256];
   __shared__ int item_s;
@@ -1479,7 +1468,7 @@ namespace tbr {
 #define TBR_INSTANTIATE_ADJOINT(T)                                                              \
   template __global__ void k_replay<T>(const StrokeRec*, const float4*, int, int, int,          \
                                        const float*, const float*, KTape, float*);              \
-  template __global__ void k_fit_fused<T>(FitJobsK, int*);
+  template __global__ void k_fit_fused<T, kFusedWaves<T>>(FitJobsK, int*);
 TBR_INSTANTIATE_RENDER(kCapsule)
 TBR_INSTANTIATE_RENDER(kCoupled)
 TBR_INSTANTIATE_RENDER(kInert)
@@ -1488,6 +1477,7 @@ TBR_INSTANTIATE_ADJOINT(kCapsule)
 TBR_INSTANTIATE_ADJOINT(kCoupled)
 TBR_INSTANTIATE_ADJOINT(kInert)
 TBR_INSTANTIATE_ADJOINT(kDrops)
+template __global__ void k_fit_fused<kCapsule, kFusedWavesLong>(FitJobsK, int*);
 #undef TBR_INSTANTIATE_RENDER
 #undef TBR_INSTANTIATE_ADJOINT
 }  // namespace tbr

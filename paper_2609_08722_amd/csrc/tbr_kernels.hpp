@@ -123,7 +123,24 @@ __global__ void k_palette_grad(const float* pal_terms, int n, int kpal, const fl
 __global__ void k_loss_final(const float* part, int n_part, float inv_count, float* loss);
 __global__ void k_adam(float* prm, const float* grd, float* m, float* v, int n, int kpal, KAdam a,
                        const int32_t* records, int capacity);
+// Waves per SIMD of the fused fit kernel (its launch bound). The forward and
+// the replay share one register allocation there, so the bound trades
+// registers for occupancy per transport, as measured at 1024^2 x 2000
+// (bitwise the same results at every bound). The capsule map at 7 waves
+// (72 VGPRs; its spills are of values that live across a tile or a
+// 16-stroke chunk, and one reload in the forward's checkpoint store) runs
+// 1.6-1.9% faster than at 6 (80 VGPRs), 4-5% faster than at 4 or 5 (98 / 96
+// VGPRs, no spill) and 5% faster than at 8 (64 VGPRs, spills in the stroke
+// loops). Programs of long strokes put many more steps on the flank's and
+// the general map's far steps, which need more registers: the fitting loop
+// of Table hyper (offsets up to 0.3 per component) runs 4.7% faster at 6
+// waves than at 7 at every stage of its annealing, so the capsule map has a
+// 6-wave instantiation for such programs (kFusedWavesLong). The coupled map,
+// with more live values, is fastest at 5; R_U and R_D run at 7.
 template <int kT>
+constexpr int kFusedWaves = kT == kCoupled ? 5 : 7;
+constexpr int kFusedWavesLong = 6;
+template <int kT, int kW>
 __global__ void k_fit_fused(FitJobsK jobs, int* cursor);
 __global__ void k_serve(const ServeDesc* descs, const uint2* items, int n_items, int* cursor);
 __global__ void k_serve_prep(const ServePrep* preps, int n_req);
