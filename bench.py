@@ -53,12 +53,14 @@ OPS_EXECUTED = {"forward": 92, "replay": 196}
 # FETCH_SIZE (x 2.0) + WRITE_SIZE (x 1.0), scaled by a 256 MiB copy measured
 # in the same runs; valid only for the kernel sources it was measured on
 # (or sources whose k_fit_fused<0> compiles to the same code).
-TRAFFIC = {"sha": "f9dbc2d4366fc3f0", "bytes": 558.5e6 + 752.8e6}
+# (Measured at hash f9dbc2d4366fc3f0; the sources of hash 6fee912361afaea3
+# differ from them in comments only and build to a byte-identical library.)
+TRAFFIC = {"sha": "6fee912361afaea3", "bytes": 558.5e6 + 752.8e6}
 # Wave-level instruction counts per k_fit_fused<0> launch at the bench
 # workload (rocprofv3 --pmc, per-dispatch averages), for the same sources
 # only: SQ_INSTS_VALU_{FMA,ADD,MUL}_F32, SQ_INSTS_VALU_TRANS_F32 and
 # SQ_INSTS_VALU. Each wave instruction does 64 lane operations.
-COUNTERS = {"sha": "f9dbc2d4366fc3f0",
+COUNTERS = {"sha": "6fee912361afaea3",
             "fma_f32": 2.626e+09, "add_f32": 7.506e+08, "mul_f32": 2.285e+09,
             "trans_f32": 3.379e+08, "valu": 7.305e+09}
 

@@ -12,8 +12,9 @@
 //   a leaf receives, and with it where the leaf's deposit ends (Leaf).
 //
 // Transcendentals: raw v_sqrt/v_rcp/v_exp (about 1 ulp) plus the
-// first-quadrant atan / sin / cos polynomials of minimax_coeffs.h (Remez
-// fits, about 1e-7 absolute in FP32). Every branch of the chart is written
+// polynomials of minimax_coeffs.h (Remez fits): 2 atan on [0, 1] for the
+// half-angle cap angle, sin and cos on [0, pi/2] (about 1e-7 absolute in
+// FP32). Every branch of the chart is written
 // branch-free: on the flank of the capsule the cap angle is exactly 0, its
 // sine 0 and cosine 1, so the cap formulas reduce to the flank ones.
 #pragma once
