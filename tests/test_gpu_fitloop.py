@@ -114,6 +114,30 @@ def test_loop_step_matches_oracle(orc):
     assert np.abs(th1 - want_th).max() <= 1e-6
 
 
+def test_loop_step_gradient_equals_fit_step():
+    """The loop step launches the capsule map's fused kernel at the launch
+    bound for long strokes (its window admits offsets up to 0.3), the fit
+    step at its own; the two builds share the code, so one loop step's data
+    gradient equals the fit step's, bit for bit, on the same natural
+    parameters, options and target."""
+    fit, th, target = loop_setup(W=256, H=192, n=400, k=8, seed=43)
+    assert fit.window.l_max > 0.1
+    n, k = fit.n, fit.k
+    fit.step_checked(target)
+    params, g_loop = fit.params.clone(), fit.grads.clone()
+    o = fit.opts
+    prog = {f: v.clone() for f, v in api.unpack(params, n, k).items()}
+    fs = api.FitState(prog, api.Opts(o.width, o.height, tau=o.tau, tau_c=o.tau_c, eps=o.eps,
+                                     ckpt=o.ckpt, side_slots=o.side_slots))
+    fs.step(target)
+    torch.cuda.synchronize()
+    got, want = api.unpack(fs.grads, n, k), api.unpack(g_loop, n, k)
+    for f in want:
+        diff = (got[f] - want[f]).abs().max().item()
+        log(f"[loop vs fit step] {f}: max diff {diff:.3e}")
+        assert torch.equal(got[f], want[f]), f
+
+
 def test_loop_fits_and_stays_in_windows():
     """50 annealed steps at 128x128: the total loss falls, every parameter
     stays in its window and the hard render of the export is the hard
